@@ -1,0 +1,197 @@
+/*
+ * gicp.h — C ABI of the MI355X (gfx950) G-ICP tracking library, libgicp.so.
+ *
+ * The library computes the tracking step of "RGBD GS-ICP SLAM" (Ha, Yeon, Yu):
+ *   1. k-nearest-neighbour search over a uniform-grid spatial hash built by
+ *      radix sort (Sec. 3: the covariance of a point is the covariance matrix
+ *      of its k nearest neighbours; correspondences come from nearest-
+ *      neighbour search);
+ *   2. per-point covariances with scale regularisation (Sec. 3.1, Scale
+ *      Regularization: C = R Lambda^2 R^T; plane form with scales (1,1,eps),
+ *      ellipse form with scales divided by their median);
+ *   3. Gauss-Newton minimisation of the Mahalanobis objective of
+ *      Eq. (MLE_for_T), sum_i d_i^T (C^t_i + R C^s_i R^T)^-1 d_i with
+ *      d_i = x^t_i - T x^s_i, reduced per iteration to a 6x6 system.
+ *
+ * Conventions shared by every call
+ * ---------------------------------
+ * Points:        const float* xyz, structure of arrays [3][n]: x[0..n), then
+ *                y[0..n), then z[0..n).  Device memory.
+ * Covariances:   float* cov, structure of arrays [6][n] in the order
+ *                xx, xy, xz, yy, yz, zz.  Device memory.
+ * Pose:          double[16], 4x4 row-major, host memory; maps source (frame)
+ *                coordinates into target (map) coordinates: q = R x + t.
+ * H, b:          double[36] full symmetric row-major and double[6], host memory,
+ *                in the tangent order [omega_x, omega_y, omega_z, v_x, v_y, v_z]
+ *                of the left perturbation T <- Exp(xi) T.  They are the sums
+ *                H = sum J^T M J, b = sum J^T M d of the last linearisation
+ *                (the one that produced the final update), J = [[q]x, -I],
+ *                M = (C^t + R C^s R^T)^-1.
+ * Streams:       every call takes a hipStream_t (passed as void*; NULL is the
+ *                default stream).  Calls that return device results are
+ *                stream-ordered and do not synchronise the host unless stated.
+ * Ownership:     every array argument is caller-owned and must stay valid
+ *                until the stream work completes; the library never frees or
+ *                retains a caller pointer past the call.  The library owns only
+ *                gicp_ctx and gicp_map objects and their workspaces, which grow
+ *                on demand and are reused (no allocation on a call whose sizes
+ *                do not exceed the largest seen so far).
+ * Threading:     a gicp_ctx is not thread-safe; use one per host thread.
+ * Errors:        every call returns a gicp_status.  No C++ exception crosses
+ *                the ABI.  Checks that need device data (non-finite inputs)
+ *                are raised by the next synchronising call on the same
+ *                context (gicp_register, gicp_sync_status).
+ */
+#ifndef GICP_H
+#define GICP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gicp_status {
+    GICP_OK = 0,
+    GICP_E_ARG = 1,         /* null pointer, n < k, k outside [1,64], n <= 0, bad mode */
+    GICP_E_NONFINITE = 2,   /* a NaN/Inf coordinate or covariance entry was seen */
+    GICP_E_NO_CORR = 3,     /* fewer than 6 correspondences within r_max */
+    GICP_E_DEGENERATE = 4,  /* Cholesky of H failed: a pivot <= 1e-12 * max(diag H) */
+    GICP_E_OOM = 5,         /* device allocation failed */
+    GICP_E_HIP = 6,         /* a HIP runtime call failed (code in gicp_stats.hip_error) */
+    GICP_E_INEXACT = 7      /* k-NN could not be proven exact (never expected; see gicp_knn) */
+} gicp_status;
+
+typedef enum gicp_reg_mode {
+    GICP_REG_NONE = 0,      /* raw k-NN covariance */
+    GICP_REG_PLANE = 1,     /* eigenvalues replaced by (1, 1, eps): I - (1 - eps) n n^T (Sec. 3.1) */
+    GICP_REG_ELLIPSE = 2    /* covariance divided by its middle eigenvalue (Sec. 3.1) */
+} gicp_reg_mode;
+
+typedef enum gicp_precision {
+    GICP_ACC_TWOSUM = 0,    /* FP32 per point, compensated two-sum per lane and
+                               wavefront, FP64 across wavefronts and blocks (default) */
+    GICP_ACC_FP32 = 1,      /* FP32 per point, plain FP32 sums everywhere (study only) */
+    GICP_ACC_FP64 = 2       /* FP32 per point, FP64 sums everywhere (study only) */
+} gicp_precision;
+
+typedef struct gicp_ctx gicp_ctx;
+typedef struct gicp_map gicp_map;
+
+typedef struct gicp_params {
+    int32_t k;              /* neighbours per source covariance (self included), default 20 */
+    float eps;              /* plane regularisation eps (covariance eigenvalue), default 1e-3 */
+    float r_max;            /* correspondence gate in metres (inclusive: d^2 <= r_max^2), default 0.1 */
+    int32_t max_it;         /* Gauss-Newton iterations, default 30 */
+    double conv_rot;        /* stop when |omega| < conv_rot [rad] ... */
+    double conv_trans;      /* ... and |v| < conv_trans [m]; 0 disables early exit */
+    int32_t reg_mode;       /* gicp_reg_mode for source covariances computed by the call */
+    float cell_src;         /* grid cell [m] for the source k-NN; <= 0: estimate (synchronises) */
+    int32_t precision;      /* gicp_precision */
+    int32_t reserved;
+} gicp_params;
+
+typedef struct gicp_stats {
+    int32_t iters;          /* Gauss-Newton iterations run */
+    int32_t n_inliers;      /* correspondences in the last linearisation */
+    double cost;            /* sum d^T M d of the last linearisation */
+    int32_t converged;      /* 1 if the step fell below (conv_rot, conv_trans) */
+    int32_t status;         /* gicp_status of the registration */
+    int32_t hip_error;      /* hipError_t of the failing runtime call, else 0 */
+    int32_t reserved;
+} gicp_stats;
+
+/* Fills a gicp_params with the defaults listed above. */
+void gicp_params_default(gicp_params* p);
+
+/* Library version string (static storage). */
+const char* gicp_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char* gicp_strerror(int status);
+
+/* Creates a context on HIP device `device` (it becomes current for the call).
+ * Allocates a small fixed workspace; larger buffers grow on demand. */
+int gicp_create(gicp_ctx** ctx, int device);
+int gicp_destroy(gicp_ctx* ctx);
+
+/* Synchronises `stream` and returns (then clears) any device-side error the
+ * context recorded (GICP_E_NONFINITE) since the last synchronising call. */
+int gicp_sync_status(gicp_ctx* ctx, void* stream);
+
+/* Estimates a grid cell size for k-NN over `pts` (n points, SoA [3][n]):
+ * the 75th percentile, over up to 256 evenly strided sample points, of the
+ * distance to the k-th nearest neighbour (brute force), times 1.1.
+ * Synchronises the stream; writes the result to *cell (host). */
+int gicp_estimate_cell(gicp_ctx* ctx, const float* pts, int64_t n, int k, float* cell, void* stream);
+
+/* k nearest neighbours of each query among `pts` (Sec. 3 nearest-neighbour
+ * search).  Ranking key: the FP32 squared distance
+ *   fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)),  dx = fl(q.x - p.x)
+ * (round to nearest, no fused multiply-add), ties broken by the lower point
+ * index.  Output row-major [nq][k]: idx (int32 point indices) and d2 (that
+ * key).  Only neighbours with key <= fl(r_max*r_max) are reported when
+ * r_max > 0; remaining slots hold idx -1 and d2 +inf.  `cell` is the grid cell
+ * size in metres (<= 0: estimated, which synchronises).  The search visits grid
+ * shells until the result is provably exact, then falls back to a full scan.
+ * Returns GICP_E_ARG for null pointers, n < 1, nq < 0 or k outside [1,64]. */
+int gicp_knn(gicp_ctx* ctx, const float* pts, int64_t n, const float* queries, int64_t nq,
+             int k, float cell, float r_max, int32_t* idx, float* d2, void* stream);
+
+/* Per-point covariances of `pts` from their k nearest neighbours, self
+ * included (Sec. 3), with scale regularisation `reg_mode` (Sec. 3.1):
+ * C = (1/k) sum_j (p_j - mu)(p_j - mu)^T over the neighbours, mu their mean;
+ * PLANE: I - (1 - eps) n n^T with n the eigenvector of the smallest
+ * eigenvalue; ELLIPSE: C / lambda_mid.  Output covs SoA [6][n] (device).
+ * Asynchronous.  `cell` as in gicp_knn.  Returns GICP_E_ARG for null pointers,
+ * n < k or k outside [1,64]. */
+int gicp_covariances(gicp_ctx* ctx, const float* pts, int64_t n, int k, float cell,
+                     int reg_mode, float eps, float* covs, void* stream);
+
+/* Builds a map handle from Gaussians (means SoA [3][m], covs SoA [6][m],
+ * device): sorts them into grid cells of size `cell` (<= 0: estimated from
+ * the 8-NN distance, which synchronises), builds the cell hash table, and
+ * applies the target regularisation `reg_mode` (eps as above) once, so that
+ * registrations against the map reuse it (Sec. 3: the map's covariances are
+ * never recomputed; Sec. 3.1: target Gaussians are regularised for tracking).
+ * The inputs may be freed once the stream has passed this call. */
+int gicp_map_build(gicp_ctx* ctx, const float* means, const float* covs, int64_t m,
+                   float cell, int reg_mode, float eps, gicp_map** out, void* stream);
+int gicp_map_destroy(gicp_map* map);
+/* Number of Gaussians and cell size of a map. */
+int gicp_map_info(const gicp_map* map, int64_t* m, float* cell);
+
+/* Registers a source cloud against a map by Gauss-Newton on Eq. MLE_for_T.
+ *   src        SoA [3][n] source points (device)
+ *   src_covs   SoA [6][n] source covariances (device), or NULL: computed with
+ *              params->k, params->reg_mode, params->eps, params->cell_src
+ *   init_pose  initial T (host, row-major 4x4)
+ *   pose, H, b outputs (host); pose holds the last valid iterate also when the
+ *              status is GICP_E_NO_CORR or GICP_E_DEGENERATE
+ *   src_covs_out  nullable SoA [6][n] (device): receives the covariances used
+ *              (the ones the paper shares with the map)
+ *   stats      nullable (host)
+ * Per iteration: q_i = R x_i + t; the nearest map mean within r_max (exact,
+ * ties to the lower map index); Sigma_i = C^t + R C^s_i R^T; accumulation of
+ * H, b, e, n over inliers; then on the device an FP64 6x6 Cholesky solve,
+ * xi = -H^-1 b, T <- Exp(xi) T, and the convergence test.  Synchronises the
+ * stream once at the end (pose, H and b are host outputs).  Non-convergence
+ * within max_it is not an error (stats->converged = 0). */
+int gicp_register(gicp_ctx* ctx, const float* src, const float* src_covs, int64_t n,
+                  const gicp_map* map, const double init_pose[16], const gicp_params* params,
+                  double pose[16], double H[36], double b[6], float* src_covs_out,
+                  gicp_stats* stats, void* stream);
+
+/* The problem statement form: builds a transient map from (map_means,
+ * map_covs, m) with cell size `map_cell` (<= 0: estimated) and no target
+ * regularisation, registers, and destroys the map. */
+int gicp_register_pair(gicp_ctx* ctx, const float* src, const float* src_covs, int64_t n,
+                       const float* map_means, const float* map_covs, int64_t m, float map_cell,
+                       const double init_pose[16], const gicp_params* params,
+                       double pose[16], double H[36], double b[6], gicp_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GICP_H */

@@ -1,0 +1,187 @@
+"""MI355X (gfx950) G-ICP tracking: thin Python binding of libgicp.so.
+
+Every step of the tracking path runs in the HIP kernels of libgicp.so; this
+module only marshals arguments.  PyTorch supplies device memory and the
+current stream.  Arrays use the library's structure-of-arrays layouts:
+points [3, n] float32, covariances [6, n] float32 (xx, xy, xz, yy, yz, zz).
+There is no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK, Params,
+                   Stats)
+
+__all__ = ["Context", "Map", "Params", "Stats", "RegisterResult", "GicpError", "params",
+           "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "to_soa", "lib"]
+
+
+class GicpError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().gicp_strerror(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+def lib():
+    return _abi.load()
+
+
+def params(**kw) -> Params:
+    """gicp_params with the library defaults, overridden by keyword."""
+    p = Params()
+    lib().gicp_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _check_f32_cuda(t, rows: int, name: str):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2 or t.shape[0] != rows:
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape [{rows}, n]")
+
+
+def to_soa(pts, device="cuda"):
+    """[n,3] (numpy or torch) -> contiguous float32 [3,n] on the device."""
+    import torch
+    t = torch.as_tensor(pts, dtype=torch.float32)
+    return t.t().contiguous().to(device)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class RegisterResult:
+    pose: np.ndarray
+    H: np.ndarray
+    b: np.ndarray
+    iters: int
+    n_inliers: int
+    cost: float
+    converged: bool
+    status: int
+
+
+class Map:
+    """Cell-sorted map Gaussians and their hash table (owned by the library)."""
+
+    def __init__(self, handle: C.c_void_p, m: int, cell: float):
+        self.handle = handle
+        self.m = m
+        self.cell = cell
+
+    def close(self):
+        if self.handle:
+            lib().gicp_map_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        st = lib().gicp_create(C.byref(h), device)
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gicp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_status(self) -> int:
+        return lib().gicp_sync_status(self.handle, _stream())
+
+    def estimate_cell(self, pts, k: int) -> float:
+        _check_f32_cuda(pts, 3, "pts")
+        c = C.c_float()
+        st = lib().gicp_estimate_cell(self.handle, _ptr(pts), pts.shape[1], k, C.byref(c), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_estimate_cell")
+        return float(c.value)
+
+    def knn(self, pts, queries, k: int, cell: float = 0.0, r_max: float = 0.0, out=None):
+        import torch
+        _check_f32_cuda(pts, 3, "pts")
+        _check_f32_cuda(queries, 3, "queries")
+        nq = queries.shape[1]
+        if out is None:
+            idx = torch.empty((nq, k), dtype=torch.int32, device=pts.device)
+            d2 = torch.empty((nq, k), dtype=torch.float32, device=pts.device)
+        else:
+            idx, d2 = out
+        st = lib().gicp_knn(self.handle, _ptr(pts), pts.shape[1], _ptr(queries), nq, k, cell, r_max,
+                            _ptr(idx), _ptr(d2), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_knn")
+        return idx, d2
+
+    def covariances(self, pts, k: int = 20, cell: float = 0.0, reg_mode: int = REG_PLANE, eps: float = 1e-3,
+                    out=None):
+        import torch
+        _check_f32_cuda(pts, 3, "pts")
+        n = pts.shape[1]
+        covs = torch.empty((6, n), dtype=torch.float32, device=pts.device) if out is None else out
+        st = lib().gicp_covariances(self.handle, _ptr(pts), n, k, cell, reg_mode, eps, _ptr(covs), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_covariances")
+        return covs
+
+    def map_build(self, means, covs, cell: float = 0.0, reg_mode: int = REG_NONE, eps: float = 1e-3) -> Map:
+        _check_f32_cuda(means, 3, "means")
+        _check_f32_cuda(covs, 6, "covs")
+        h = C.c_void_p()
+        st = lib().gicp_map_build(self.handle, _ptr(means), _ptr(covs), means.shape[1], cell, reg_mode, eps,
+                                  C.byref(h), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_map_build")
+        m = C.c_int64()
+        c = C.c_float()
+        lib().gicp_map_info(h, C.byref(m), C.byref(c))
+        return Map(h, int(m.value), float(c.value))
+
+    def register(self, src, gmap: Map, init_pose, prm: Params | None = None, src_covs=None,
+                 src_covs_out=None, raise_on_error: bool = False) -> RegisterResult:
+        _check_f32_cuda(src, 3, "src")
+        if src_covs is not None:
+            _check_f32_cuda(src_covs, 6, "src_covs")
+        if src_covs_out is not None:
+            _check_f32_cuda(src_covs_out, 6, "src_covs_out")
+        prm = prm or params()
+        init = _abi.D16(*np.asarray(init_pose, np.float64).reshape(16))
+        pose, H, b = _abi.D16(), _abi.D36(), _abi.D6()
+        stats = Stats()
+        st = lib().gicp_register(self.handle, _ptr(src), _ptr(src_covs), src.shape[1], gmap.handle, init,
+                                 C.byref(prm), pose, H, b, _ptr(src_covs_out), C.byref(stats), _stream())
+        if st == _abi.GICP_E_ARG or st in (_abi.GICP_E_HIP, _abi.GICP_E_OOM) or (raise_on_error and st != GICP_OK):
+            raise GicpError(st, "gicp_register")
+        return RegisterResult(np.array(pose[:]).reshape(4, 4), np.array(H[:]).reshape(6, 6), np.array(b[:]),
+                              stats.iters, stats.n_inliers, stats.cost, bool(stats.converged), st)

@@ -1,0 +1,101 @@
+// Shared device/host definitions of the gfx950 G-ICP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gicp.h"
+
+namespace gicp {
+
+constexpr int kBlock = 256;           // threads per workgroup for the point kernels
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+constexpr int kCellBits = 10;         // wrapped cell coordinate bits per axis (30-bit keys)
+constexpr uint32_t kCellMask = (1u << kCellBits) - 1u;
+constexpr int kMaxShell = 8;          // grid shells searched before the full-scan fallback
+constexpr int kNumAcc = 29;           // 21 unique H terms, 6 b terms, cost, inlier count
+
+// Error bits recorded on the device (context error word).
+constexpr int kErrNonFinite = 1;
+constexpr int kErrInexact = 2;
+
+// ---------------------------------------------------------------------------
+// Grid cells.  A point p lies in cell floor(p * inv_h) per axis; the cell key
+// packs the three cell coordinates modulo 1024 (10 bits each).  Wrapping
+// cannot break exactness: candidates are always ranked by their real
+// distance, and an aliased cell only adds far-away candidates.
+// ---------------------------------------------------------------------------
+struct Cell {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Cell cell_of(float x, float y, float z, float inv_h) {
+    Cell c;
+    c.x = (int)floorf(x * inv_h);
+    c.y = (int)floorf(y * inv_h);
+    c.z = (int)floorf(z * inv_h);
+    return c;
+}
+
+__device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz) {
+    return ((uint32_t)cx & kCellMask) | (((uint32_t)cy & kCellMask) << kCellBits) |
+           (((uint32_t)cz & kCellMask) << (2 * kCellBits));
+}
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t mask) {
+    return (key * 2654435761u) & mask;  // Knuth multiplicative hashing
+}
+
+// Cell table lookup: entry = {key, start, count, -}.  Returns count (0 if the
+// cell is empty) and writes its start offset into the cell-sorted arrays.
+__device__ __forceinline__ uint32_t cell_lookup(const uint4* __restrict__ table, uint32_t mask,
+                                                uint32_t key, uint32_t& start) {
+    uint32_t s = hash_slot(key, mask);
+    while (true) {
+        const uint4 e = table[s];
+        if (e.x == key) {
+            start = e.y;
+            return e.z;
+        }
+        if (e.x == kEmptyKey) return 0u;
+        s = (s + 1u) & mask;
+    }
+}
+
+// FP32 ranking key of the k-NN: fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)) with
+// dx = fl(q.x - p.x), every operation rounded on its own (no contraction into
+// fused multiply-adds), so that the ranking is reproducible bit for bit.
+__device__ __forceinline__ float rank_key(float qx, float qy, float qz, float px, float py, float pz) {
+#pragma clang fp contract(off)
+    const float dx = qx - px;
+    const float dy = qy - py;
+    const float dz = qz - pz;
+    const float s = dx * dx + dy * dy;
+    return s + dz * dz;
+}
+
+// (key, index) packed so that unsigned integer order is the lexicographic
+// order: non-negative floats order like their bit patterns.
+__device__ __forceinline__ uint64_t lex(float key, uint32_t idx) {
+    return ((uint64_t)__float_as_uint(key) << 32) | (uint64_t)idx;
+}
+
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+    return isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+// Distance from q to the boundary of the block of cells [c - R, c + R] per
+// axis, minus a safety margin that covers the rounding of the cell
+// assignment, and the FP32 key bound below which every point outside the
+// block is provably ranked after the current k-th neighbour.
+__device__ __forceinline__ float block_clearance(float qx, float qy, float qz, Cell c, int R, float h) {
+    const float lox = (float)(c.x - R) * h, hix = (float)(c.x + R + 1) * h;
+    const float loy = (float)(c.y - R) * h, hiy = (float)(c.y + R + 1) * h;
+    const float loz = (float)(c.z - R) * h, hiz = (float)(c.z + R + 1) * h;
+    float d = fminf(fminf(qx - lox, hix - qx), fminf(fminf(qy - loy, hiy - qy), fminf(qz - loz, hiz - qz)));
+    const float mag = fmaxf(fmaxf(fabsf(qx), fabsf(qy)), fabsf(qz)) + (float)(R + 1) * h;
+    d = d - 4e-6f * mag - 1e-6f * h;   // cell rounding slack (relative 4e-6 of the coordinate scale)
+    return d;
+}
+
+}  // namespace gicp

@@ -1,0 +1,440 @@
+// Gauss-Newton iteration of G-ICP (Sec. 3, Eq. MLE_for_T):
+//   k_gn_linearize : per source point, q = R x + t, the nearest map mean within
+//                    r_max (exact over the map's cell grid, ties to the lower
+//                    map index), Sigma = C_t + R C_s R^T, M = Sigma^-1,
+//                    J = [[q]x, -I]; accumulation of the 21 unique terms of
+//                    J^T M J, the 6 of J^T M d, d^T M d and the inlier count.
+//                    FP32 per point; per-lane and per-wavefront sums are
+//                    compensated (two-sum), the per-wave totals are summed in
+//                    FP64 and written as one FP64 partial per workgroup.
+//   k_gn_solve     : one workgroup; FP64 sum of the partials in a fixed order,
+//                    6x6 Cholesky, xi = -H^-1 b, T <- Exp(xi) T, convergence.
+// A registration runs (linearize, solve) max_it times; once the solve marks
+// the state done, later launches return immediately.
+#include <float.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace gicp {
+
+namespace {
+
+// Knuth's two-sum: s + x = t + err exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& t, float& err) {
+    t = a + b;
+    const float bp = t - a;
+    err = (a - (t - bp)) + (b - bp);
+}
+
+template <int ACC>
+struct Acc;
+
+template <>
+struct Acc<GICP_ACC_TWOSUM> {
+    float s[kNumAcc], c[kNumAcc];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j) s[j] = c[j] = 0.f;
+    }
+    __device__ __forceinline__ void add(int j, float x) {
+        float t, e;
+        two_sum(s[j], x, t, e);
+        s[j] = t;
+        c[j] += e;
+    }
+    __device__ __forceinline__ void wave_reduce() {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const float s2 = __shfl_xor(s[j], o, 64);
+                const float c2 = __shfl_xor(c[j], o, 64);
+                float t, e;
+                two_sum(s[j], s2, t, e);
+                s[j] = t;
+                c[j] = c[j] + c2 + e;
+            }
+        }
+    }
+    __device__ __forceinline__ double total(int j) const { return (double)s[j] + (double)c[j]; }
+};
+
+template <>
+struct Acc<GICP_ACC_FP32> {
+    float s[kNumAcc];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j) s[j] = 0.f;
+    }
+    __device__ __forceinline__ void add(int j, float x) { s[j] += x; }
+    __device__ __forceinline__ void wave_reduce() {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
+    }
+    __device__ __forceinline__ double total(int j) const { return (double)s[j]; }
+};
+
+template <>
+struct Acc<GICP_ACC_FP64> {
+    double s[kNumAcc];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j) s[j] = 0.0;
+    }
+    __device__ __forceinline__ void add(int j, float x) { s[j] += (double)x; }
+    __device__ __forceinline__ void wave_reduce() {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
+    }
+    __device__ __forceinline__ double total(int j) const { return s[j]; }
+};
+
+// Exact 1-NN of q among the map means within the gate; returns the sorted
+// position (or -1).  Ranking by (FP32 key, original index).
+__device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz) {
+    const GridView& g = m.g;
+    uint64_t best = ~0ull;
+    int32_t pos = -1;
+    const Cell c = cell_of(qx, qy, qz, g.inv_h);
+    auto scan = [&](int cx, int cy, int cz) {
+        uint32_t start = 0;
+        const uint32_t cnt = cell_lookup(g.table, g.mask, cell_key(cx, cy, cz), start);
+        for (uint32_t j = 0; j < cnt; ++j) {
+            const float4 p = g.spts[start + j];
+            const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
+            const uint64_t v = lex(d2, __float_as_uint(p.w));
+            if (v < best) {
+                best = v;
+                pos = (int32_t)(start + j);
+            }
+        }
+    };
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) scan(c.x + dx, c.y + dy, c.z + dz);
+    const float r_gate = m.r_max * 1.000001f + 1e-6f;
+    bool done = false;
+    for (int R = 1; !done; ++R) {
+        const float clr = block_clearance(qx, qy, qz, c, R, g.h);
+        if (clr > 0.f) {
+            if (clr >= r_gate) break;
+            if (best != ~0ull) {
+                const float bk = __uint_as_float((uint32_t)(best >> 32));
+                if (bk < clr * clr * (1.f - 1e-6f)) break;
+            }
+        }
+        if (R >= kMaxShell) {
+            // full scan (exact by construction)
+            best = ~0ull;
+            pos = -1;
+            for (int32_t j = 0; j < g.n; ++j) {
+                const float4 p = g.spts[j];
+                const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
+                if (v < best) {
+                    best = v;
+                    pos = j;
+                }
+            }
+            done = true;
+            break;
+        }
+        const int S = R + 1;
+        for (int dz = -S; dz <= S; ++dz)
+            for (int dy = -S; dy <= S; ++dy)
+                for (int dx = -S; dx <= S; ++dx)
+                    if (max(max(abs(dx), abs(dy)), abs(dz)) == S) scan(c.x + dx, c.y + dy, c.z + dz);
+    }
+    if (pos < 0) return -1;
+    const float bk = __uint_as_float((uint32_t)(best >> 32));
+    return (bk <= m.r_max2) ? pos : -1;
+}
+
+template <int ACC>
+__global__ __launch_bounds__(kBlock) void k_gn_linearize(const float* __restrict__ src,
+                                                         const float* __restrict__ scov, int64_t n, MapView map,
+                                                         const RegState* __restrict__ st,
+                                                         double* __restrict__ partials) {
+    if (st->done) return;
+    float R[9], t[3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
+
+    Acc<ACC> acc;
+    acc.zero();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = src[i], y = src[n + i], z = src[2 * n + i];
+        const float qx = R[0] * x + R[1] * y + R[2] * z + t[0];
+        const float qy = R[3] * x + R[4] * y + R[5] * z + t[1];
+        const float qz = R[6] * x + R[7] * y + R[8] * z + t[2];
+        const int32_t pos = nearest(map, qx, qy, qz);
+        if (pos < 0) continue;
+        const float4 mu = map.g.spts[pos];
+        const float4 ca = map.scov[2 * pos];
+        const float4 cb = map.scov[2 * pos + 1];
+        // source covariance rotated: A = R Cs, S = A R^T
+        const float c00 = scov[i], c01 = scov[n + i], c02 = scov[2 * n + i];
+        const float c11 = scov[3 * n + i], c12 = scov[4 * n + i], c22 = scov[5 * n + i];
+        const float a00 = R[0] * c00 + R[1] * c01 + R[2] * c02;
+        const float a01 = R[0] * c01 + R[1] * c11 + R[2] * c12;
+        const float a02 = R[0] * c02 + R[1] * c12 + R[2] * c22;
+        const float a10 = R[3] * c00 + R[4] * c01 + R[5] * c02;
+        const float a11 = R[3] * c01 + R[4] * c11 + R[5] * c12;
+        const float a12 = R[3] * c02 + R[4] * c12 + R[5] * c22;
+        const float a20 = R[6] * c00 + R[7] * c01 + R[8] * c02;
+        const float a21 = R[6] * c01 + R[7] * c11 + R[8] * c12;
+        const float a22 = R[6] * c02 + R[7] * c12 + R[8] * c22;
+        const float s00 = ca.x + a00 * R[0] + a01 * R[1] + a02 * R[2];
+        const float s01 = ca.y + a00 * R[3] + a01 * R[4] + a02 * R[5];
+        const float s02 = ca.z + a00 * R[6] + a01 * R[7] + a02 * R[8];
+        const float s11 = ca.w + a10 * R[3] + a11 * R[4] + a12 * R[5];
+        const float s12 = cb.x + a10 * R[6] + a11 * R[7] + a12 * R[8];
+        const float s22 = cb.y + a20 * R[6] + a21 * R[7] + a22 * R[8];
+        // M = Sigma^-1 by cofactors
+        const float k00 = s11 * s22 - s12 * s12;
+        const float k01 = s02 * s12 - s01 * s22;
+        const float k02 = s01 * s12 - s02 * s11;
+        const float det = s00 * k00 + s01 * k01 + s02 * k02;
+        if (!(det > 0.f)) continue;
+        const float id = 1.f / det;
+        const float m00 = k00 * id, m01 = k01 * id, m02 = k02 * id;
+        const float m11 = (s00 * s22 - s02 * s02) * id;
+        const float m12 = (s01 * s02 - s00 * s12) * id;
+        const float m22 = (s00 * s11 - s01 * s01) * id;
+        // residual
+        const float dx = mu.x - qx, dy = mu.y - qy, dz = mu.z - qz;
+        const float md0 = m00 * dx + m01 * dy + m02 * dz;
+        const float md1 = m01 * dx + m11 * dy + m12 * dz;
+        const float md2 = m02 * dx + m12 * dy + m22 * dz;
+        // B = M [q]x, [q]x = [[0,-qz,qy],[qz,0,-qx],[-qy,qx,0]]
+        const float b00 = m01 * qz - m02 * qy, b01 = m02 * qx - m00 * qz, b02 = m00 * qy - m01 * qx;
+        const float b10 = m11 * qz - m12 * qy, b11 = m12 * qx - m01 * qz, b12 = m01 * qy - m11 * qx;
+        const float b20 = m12 * qz - m22 * qy, b21 = m22 * qx - m02 * qz, b22 = m02 * qy - m12 * qx;
+        // H_ww = [q]x^T B: row i of [q]x^T is column i of [q]x
+        // column 0 of [q]x = (0, qz, -qy); column 1 = (-qz, 0, qx); column 2 = (qy, -qx, 0)
+        const float h00 = qz * b10 - qy * b20;
+        const float h01 = qz * b11 - qy * b21;
+        const float h02 = qz * b12 - qy * b22;
+        const float h11 = -qz * b01 + qx * b21;
+        const float h12 = -qz * b02 + qx * b22;
+        const float h22 = qy * b02 - qx * b12;
+        // H_wv = -B^T, H_vv = M
+        acc.add(0, h00); acc.add(1, h01); acc.add(2, h02);
+        acc.add(3, -b00); acc.add(4, -b10); acc.add(5, -b20);
+        acc.add(6, h11); acc.add(7, h12);
+        acc.add(8, -b01); acc.add(9, -b11); acc.add(10, -b21);
+        acc.add(11, h22);
+        acc.add(12, -b02); acc.add(13, -b12); acc.add(14, -b22);
+        acc.add(15, m00); acc.add(16, m01); acc.add(17, m02);
+        acc.add(18, m11); acc.add(19, m12);
+        acc.add(20, m22);
+        // b = [ [q]x^T M d ; -M d ],  [q]x^T v = v x q
+        acc.add(21, md1 * qz - md2 * qy);
+        acc.add(22, md2 * qx - md0 * qz);
+        acc.add(23, md0 * qy - md1 * qx);
+        acc.add(24, -md0); acc.add(25, -md1); acc.add(26, -md2);
+        acc.add(27, dx * md0 + dy * md1 + dz * md2);
+        acc.add(28, 1.f);
+    }
+    acc.wave_reduce();
+    __shared__ double s_w[kBlock / 64][kNumAcc];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < kNumAcc; ++j) s_w[wave][j] = acc.total(j);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumAcc) {
+        double v;
+        if (ACC == GICP_ACC_FP32) {
+            float f = 0.f;
+            for (int w = 0; w < kBlock / 64; ++w) f += (float)s_w[w][threadIdx.x];
+            v = (double)f;
+        } else {
+            v = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) v += s_w[w][threadIdx.x];
+        }
+        partials[(int64_t)blockIdx.x * kNumAcc + threadIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 solve and update.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void exp_se3(const double xi[6], double T[16]) {
+    const double wx = xi[0], wy = xi[1], wz = xi[2];
+    const double th2 = wx * wx + wy * wy + wz * wz;
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-4) {
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+        const double sn = sin(th), cs = cos(th);
+        A = sn / th;
+        B = (1.0 - cs) / th2;
+        C = (th - sn) / (th2 * th);
+    }
+    const double W[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
+    double W2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) W2[3 * i + j] = W[3 * i] * W[j] + W[3 * i + 1] * W[3 + j] + W[3 * i + 2] * W[6 + j];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            const double id = (i == j) ? 1.0 : 0.0;
+            T[4 * i + j] = id + A * W[3 * i + j] + B * W2[3 * i + j];
+        }
+        double v = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double id = (i == j) ? 1.0 : 0.0;
+            v += (id + B * W[3 * i + j] + C * W2[3 * i + j]) * xi[3 + j];
+        }
+        T[4 * i + 3] = v;
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+}
+
+constexpr int kSolveThreads = 256;
+constexpr int kSolveParts = 8;
+
+__global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __restrict__ partials, int nblocks,
+                                                            RegState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double s_part[kNumAcc][kSolveParts];
+    const int acc = st->acc;
+    const int t = threadIdx.x;
+    if (t < kNumAcc * kSolveParts) {
+        const int j = t / kSolveParts, p = t % kSolveParts;
+        if (acc == GICP_ACC_FP32) {
+            float f = 0.f;
+            for (int b = p; b < nblocks; b += kSolveParts) f += (float)partials[(int64_t)b * kNumAcc + j];
+            s_part[j][p] = (double)f;
+        } else {
+            double v = 0.0;
+            for (int b = p; b < nblocks; b += kSolveParts) v += partials[(int64_t)b * kNumAcc + j];
+            s_part[j][p] = v;
+        }
+    }
+    __syncthreads();
+    if (t != 0) return;
+    double v[kNumAcc];
+    for (int j = 0; j < kNumAcc; ++j) {
+        if (acc == GICP_ACC_FP32) {
+            float f = 0.f;
+            for (int p = 0; p < kSolveParts; ++p) f += (float)s_part[j][p];
+            v[j] = (double)f;
+        } else {
+            double s = 0.0;
+            for (int p = 0; p < kSolveParts; ++p) s += s_part[j][p];
+            v[j] = s;
+        }
+    }
+    double H[36];
+    int q = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            H[6 * i + j] = v[q];
+            H[6 * j + i] = v[q];
+            ++q;
+        }
+    for (int j = 0; j < 21; ++j) st->H[j] = v[j];
+    for (int j = 0; j < 6; ++j) st->b[j] = v[21 + j];
+    st->cost = v[27];
+    st->n_inl = v[28];
+    st->iters += 1;
+    if (v[28] < 6.0) {
+        st->status = GICP_E_NO_CORR;
+        st->done = 1;
+        return;
+    }
+    // Cholesky H = L L^T; a pivot not above 1e-12 * max(diag H) fails
+    double dmax = 0.0;
+    for (int i = 0; i < 6; ++i) dmax = fmax(dmax, H[7 * i]);
+    const double floor_ = 1e-12 * dmax;
+    double L[36];
+    for (int i = 0; i < 36; ++i) L[i] = 0.0;
+    for (int j = 0; j < 6; ++j) {
+        double s = H[7 * j];
+        for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+        if (!(s > floor_) || !isfinite(s)) {
+            st->status = GICP_E_DEGENERATE;
+            st->done = 1;
+            return;
+        }
+        L[7 * j] = sqrt(s);
+        for (int i = j + 1; i < 6; ++i) {
+            double r = H[6 * i + j];
+            for (int k = 0; k < j; ++k) r -= L[6 * i + k] * L[6 * j + k];
+            L[6 * i + j] = r / L[7 * j];
+        }
+    }
+    double y[6], xi[6];
+    for (int i = 0; i < 6; ++i) {
+        double r = v[21 + i];
+        for (int k = 0; k < i; ++k) r -= L[6 * i + k] * y[k];
+        y[i] = r / L[7 * i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double r = y[i];
+        for (int k = i + 1; k < 6; ++k) r -= L[6 * k + i] * xi[k];
+        xi[i] = r / L[7 * i];
+    }
+    for (int i = 0; i < 6; ++i) xi[i] = -xi[i];
+    double E[16], T[16];
+    exp_se3(xi, E);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += E[4 * i + k] * st->pose[4 * k + j];
+            T[4 * i + j] = s;
+        }
+    for (int i = 0; i < 16; ++i) st->pose[i] = T[i];
+    const double nw = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+    const double nv = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+    if (nw < st->conv_rot && nv < st->conv_trans) {
+        st->converged = 1;
+        st->done = 1;
+    } else if (st->iters >= st->max_it) {
+        st->done = 1;
+    }
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) st->Rf[3 * i + j] = (float)T[4 * i + j];
+        st->tf[i] = (float)T[4 * i + 3];
+    }
+}
+
+}  // namespace
+
+int gn_blocks(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+hipError_t launch_gn_iteration(const float* src, const float* scov, int64_t n, const MapView& map, RegState* st,
+                               double* partials, int nblocks, int acc, hipStream_t s) {
+    switch (acc) {
+        case GICP_ACC_FP32:
+            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_FP32>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
+                               (const RegState*)st, partials);
+            break;
+        case GICP_ACC_FP64:
+            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_FP64>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
+                               (const RegState*)st, partials);
+            break;
+        default:
+            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_TWOSUM>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
+                               (const RegState*)st, partials);
+    }
+    hipLaunchKernelGGL(k_gn_solve, dim3(1), dim3(kSolveThreads), 0, s, (const double*)partials, nblocks, st);
+    return hipGetLastError();
+}
+
+}  // namespace gicp

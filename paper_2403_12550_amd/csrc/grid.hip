@@ -1,0 +1,295 @@
+// Uniform-grid spatial hash: cell keys, a stable LSD radix sort of 30-bit keys
+// (three 10-bit digits), and the open-addressing cell table.
+//
+// Radix sort design for wave64: each pass is (1) a per-tile digit histogram,
+// (2) an exclusive scan over the digit-major [1024][tiles] count matrix, and
+// (3) a stable scatter.  Within a tile, elements are processed in rounds of
+// 256 (one per lane, in order); lanes holding the same digit are found with
+// ten wavefront ballots, their rank is the popcount of the lower lanes of the
+// match mask, and per-wave digit totals in LDS order the four waves.  Equal
+// digits therefore keep input order, which makes the sort stable.
+#include <algorithm>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace gicp {
+
+namespace {
+
+constexpr int kDigitBits = 10;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kIpt = 16;                       // rounds (elements per thread) per tile
+constexpr int kTile = kSortThreads * kIpt;     // 4096
+constexpr int kScanThreads = 1024;
+constexpr int kScanIpt = 16;
+constexpr int kScanChunk = kScanThreads * kScanIpt;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Lanes of this wavefront whose (valid) digit equals mine.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kDigitBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                          int shift, int ntiles, uint32_t* __restrict__ counts) {
+    __shared__ uint32_t s_hist[kDigits];
+    for (int i = threadIdx.x; i < kDigits; i += kSortThreads) s_hist[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kIpt; ++r) {
+        const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (keys[i] >> shift) & (kDigits - 1) : 0u;
+        const uint64_t m = match_digit(d, valid);
+        if (valid && (m & lanemask_lt()) == 0) atomicAdd(&s_hist[d], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kDigits; i += kSortThreads) counts[(int64_t)i * ntiles + blockIdx.x] = s_hist[i];
+}
+
+// Block-wide exclusive scan of one value per thread (1024 threads).
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t w = threadIdx.x < kScanThreads / 64 ? s_wave[threadIdx.x] : 0u;
+        uint32_t z = w;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(z, o, 64);
+            if ((int)threadIdx.x >= o) z += y;
+        }
+        if (threadIdx.x < kScanThreads / 64) s_wave[threadIdx.x] = z - w;  // exclusive wave offsets
+        if (threadIdx.x == kScanThreads / 64 - 1) s_wave[kScanThreads / 64] = z;
+    }
+    __syncthreads();
+    total = s_wave[kScanThreads / 64];
+    const uint32_t r = s_wave[wave] + x - v;
+    __syncthreads();
+    return r;
+}
+
+// Phase 1: sums of chunks of kScanChunk counts.
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t c,
+                                                              uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_wave[kScanThreads / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanIpt;
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j)
+        if (base + j < c) v += in[base + j];
+    uint32_t total;
+    block_exscan(v, s_wave, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Phase 2/3: exclusive scan of chunks, each offset by the exclusive prefix of
+// the chunk sums (computed in-block from `sums`, nchunks <= 1024*16).
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in, int64_t c,
+                                                            const uint32_t* __restrict__ sums, int nchunks,
+                                                            uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_wave[kScanThreads / 64 + 1];
+    __shared__ uint32_t s_off;
+    // offset of this chunk: sum of sums[0 .. blockIdx.x)
+    if (sums != nullptr) {
+        uint32_t v = 0;
+        for (int j = threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) v += sums[j];
+        uint32_t total;
+        block_exscan(v, s_wave, total);
+        if (threadIdx.x == 0) s_off = total;
+    } else if (threadIdx.x == 0) {
+        s_off = 0;
+    }
+    __syncthreads();
+    const uint32_t off = s_off;
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanIpt;
+    uint32_t loc[kScanIpt];
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        loc[j] = (base + j < c) ? in[base + j] : 0u;
+        v += loc[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exscan(v, s_wave, total) + off;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        if (base + j < c) out[base + j] = run;
+        run += loc[j];
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                             const uint32_t* __restrict__ vin, int64_t n,
+                                                             int shift, int ntiles,
+                                                             const uint32_t* __restrict__ offsets,
+                                                             uint32_t* __restrict__ kout,
+                                                             uint32_t* __restrict__ vout) {
+    __shared__ uint32_t s_base[kDigits];
+    __shared__ uint32_t s_wcount[kSortWaves][kDigits];
+    for (int i = threadIdx.x; i < kDigits; i += kSortThreads) {
+        s_base[i] = offsets[(int64_t)i * ntiles + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) s_wcount[w][i] = 0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kIpt; ++r) {
+        const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (key >> shift) & (kDigits - 1);
+        const uint64_t m = match_digit(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
+        const uint32_t cnt = (uint32_t)__popcll(m);
+        const bool leader = valid && rank == 0;
+        if (leader) s_wcount[wave][d] = cnt;
+        __syncthreads();
+        if (valid) {
+            uint32_t off = s_base[d] + rank;
+            for (int w = 0; w < wave; ++w) off += s_wcount[w][d];
+            if (off < (uint64_t)n) {   // always true for a consistent scan; guards the write
+                kout[off] = key;
+                vout[off] = val;
+            }
+        }
+        __syncthreads();
+        if (leader) {
+            atomicAdd(&s_base[d], cnt);
+            s_wcount[wave][d] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_cell_keys(const float* __restrict__ xyz, int64_t n, int64_t stride, float inv_h,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int* err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = xyz[i], y = xyz[stride + i], z = xyz[2 * stride + i];
+    if (!finite3(x, y, z)) atomicOr(err, kErrNonFinite);
+    const Cell c = cell_of(x, y, z, inv_h);
+    keys[i] = cell_key(c.x, c.y, c.z);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_table_clear(uint4* __restrict__ table, uint32_t cap) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cap) table[i] = make_uint4(kEmptyKey, 0u, 0u, 0u);
+}
+
+__global__ void k_table_build(const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals, int64_t n,
+                              const float* __restrict__ xyz, int64_t stride, float4* __restrict__ spts,
+                              uint4* __restrict__ table, uint32_t mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t v = svals[i];
+    if (v >= (uint64_t)n) v = 0;   // always a permutation; guards the gather
+    spts[i] = make_float4(xyz[v], xyz[stride + v], xyz[2 * stride + v], __uint_as_float(v));
+    const uint32_t key = skeys[i];
+    if (i == 0 || skeys[i - 1] != key) {
+        uint32_t cnt = 1;
+        while (i + cnt < n && skeys[i + cnt] == key) ++cnt;
+        uint32_t s = hash_slot(key, mask);
+        while (true) {
+            const uint32_t prev = atomicCAS(&table[s].x, kEmptyKey, key);
+            if (prev == kEmptyKey) {
+                table[s].y = (uint32_t)i;
+                table[s].z = cnt;
+                break;
+            }
+            s = (s + 1u) & mask;
+        }
+    }
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+size_t radix_scratch_bytes(int64_t n) {
+    const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, kTile));
+    const int64_t c = ntiles * kDigits;
+    const int64_t nchunks = ceil_div(c, kScanChunk);
+    return (size_t)(2 * c + nchunks + 64) * sizeof(uint32_t);
+}
+
+hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
+                         void* scratch, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int ntiles = (int)ceil_div(n, kTile);
+    const int64_t c = (int64_t)ntiles * kDigits;
+    const int nchunks = (int)ceil_div(c, kScanChunk);
+    if (nchunks > kScanThreads * 64) return hipErrorInvalidValue;
+    uint32_t* counts = static_cast<uint32_t*>(scratch);
+    uint32_t* offs = counts + c;
+    uint32_t* sums = offs + c;
+    uint32_t* kin = keys_a;
+    uint32_t* vin = vals_a;
+    uint32_t* kout = keys_b;
+    uint32_t* vout = vals_b;
+    for (int pass = 0; pass < 3; ++pass) {
+        const int shift = pass * kDigitBits;
+        hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n, shift, ntiles, counts);
+        if (nchunks > 1) {
+            hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(kScanThreads), 0, s, counts, c, sums);
+            hipLaunchKernelGGL(k_scan_down, dim3(nchunks), dim3(kScanThreads), 0, s, counts, c,
+                               (const uint32_t*)sums, nchunks, offs);
+        } else {
+            hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, s, counts, c,
+                               (const uint32_t*)nullptr, 1, offs);
+        }
+        hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, kin, vin, n, shift, ntiles,
+                           (const uint32_t*)offs, kout, vout);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    // three passes: the result sits in (keys_b, vals_b)
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_keys(const float* xyz, int64_t n, int64_t stride, float inv_h, uint32_t* keys,
+                            uint32_t* vals, int* err, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_keys, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, xyz, n, stride, inv_h, keys,
+                       vals, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_clear(uint4* table, uint32_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_table_clear, dim3((cap + 255) / 256), dim3(256), 0, s, table, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int64_t n, const float* xyz,
+                              int64_t stride, float4* spts, uint4* table, uint32_t mask, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_table_build, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, skeys, svals, n, xyz,
+                       stride, spts, table, mask);
+    return hipGetLastError();
+}
+
+}  // namespace gicp

@@ -1,0 +1,76 @@
+// Host-side launchers of the gfx950 kernels (internal to libgicp.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace gicp {
+
+// Scratch the radix sort needs for n keys (bytes), and the launcher.  Sorts
+// 30-bit keys with their values stably: (keys_a, vals_a) -> (keys_b, vals_b);
+// keys_a/vals_a are clobbered.
+size_t radix_scratch_bytes(int64_t n);
+hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
+                         int64_t n, void* scratch, hipStream_t s);
+
+// Grid over n points (SoA [3][stride]): keys + identity values.
+hipError_t launch_cell_keys(const float* xyz, int64_t n, int64_t stride, float inv_h,
+                            uint32_t* keys, uint32_t* vals, int* err, hipStream_t s);
+// Fill the hash table with empty entries.
+hipError_t launch_table_clear(uint4* table, uint32_t cap, hipStream_t s);
+// Gather points into cell order (float4 x,y,z,orig) and insert cell runs.
+hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int64_t n, const float* xyz,
+                              int64_t stride, float4* spts, uint4* table, uint32_t mask, hipStream_t s);
+
+// A built grid: cell-sorted points and the cell table.
+struct GridView {
+    const float4* spts;   // [n] x, y, z, original index (bits)
+    const uint4* table;   // [mask+1] {key, start, count, -}
+    uint32_t mask;
+    int32_t n;
+    float h, inv_h;
+};
+
+// Fused self k-NN + covariance + regularisation; covs SoA [6][n] in original order.
+hipError_t launch_knn_cov(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps,
+                          float* covs, int* err, hipStream_t s);
+// k-NN of arbitrary queries (SoA [3][nq]); idx/d2 row-major [nq][k].
+hipError_t launch_knn_query(const GridView& g, const float* q, int64_t nq, int k, float r_max,
+                            int32_t* idx, float* d2, int* err, hipStream_t s);
+// k-th neighbour distance of `ns` evenly strided samples by brute force.
+hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s);
+// Map Gaussians: regularise covariances and store them in cell order (2 x float4 each).
+hipError_t launch_map_covs(const uint32_t* svals, int64_t m, const float* covs, int64_t stride, int mode,
+                           float eps, float4* scov, int* err, hipStream_t s);
+
+// Device state of one registration.
+struct __align__(256) RegState {
+    double pose[16];
+    double H[21];
+    double b[6];
+    double cost;
+    double n_inl;
+    double conv_rot, conv_trans;
+    float Rf[9];
+    float tf[3];
+    int32_t iters;
+    int32_t max_it;
+    int32_t done;
+    int32_t status;
+    int32_t converged;
+    int32_t acc;
+};
+
+struct MapView {
+    GridView g;
+    const float4* scov;   // [m][2]: {xx, xy, xz, yy}, {yz, zz, 0, 0}
+    float r_max, r_max2;
+};
+
+int gn_blocks(int64_t n);
+hipError_t launch_gn_iteration(const float* src, const float* scov, int64_t n, const MapView& map,
+                               RegState* st, double* partials, int nblocks, int acc, hipStream_t s);
+
+}  // namespace gicp
