@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Frame-to-map G-ICP tracking benchmark on one MI355X.
+
+Workload: synthetic 1200x680 depth frames (pinhole fx=fy=600) rendered along a
+100-frame smooth trajectory in a procedural room with 40 boxes and spheres,
+1 % invalid pixels, sigma_z = 1 mm * z^2, voxel-downsampled at 2 cm (about 60k
+points per frame), registered against a 1M-Gaussian map of the same scene;
+k = 20 plane-regularised source covariances, r_max = 0.1 m, at most 20
+Gauss-Newton iterations per frame (stop below 1e-6 rad / 1e-6 m), constant-
+velocity initial poses.
+
+A step is one frame: the source grid build, the fused k-NN covariance, and
+every Gauss-Newton iteration (correspondences, linearisation, FP64 solve and
+update).  Frames and the map are resident in HBM before the timed region;
+the map is built once (timed separately).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per unit of work ("Kernels and rooflines")
+BYTES_PER_UNIT = {
+    0: 72.0,   # linearisation: src xyz 12 + src cov 24 + map mean 12 + map cov 24, per point per iteration
+    1: 36.0,   # k-NN covariance: xyz 12 in + cov 24 out, per point
+    2: 20.0,   # grid build: xyz 12 in + key/index 8 out, per point (compulsory part)
+    3: 232.0,  # solve: 29 FP64 partials per ... (negligible)
+}
+GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix sort, table)", 3: "k_gn_solve"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pose_delta(Ta, Tb):
+    """(rotation angle of Ra^T Rb [rad], |ta - tb| [m]); the angle from atan2 of
+    the skew and symmetric parts stays accurate for tiny rotations."""
+    R = Ta[:3, :3].T @ Tb[:3, :3]
+    s = 0.5 * np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    c = 0.5 * (np.trace(R) - 1.0)
+    return float(np.arctan2(s, c)), float(np.linalg.norm(Ta[:3, 3] - Tb[:3, 3]))
+
+
+def cv_init(seq, est, i):
+    """Constant-velocity prediction from the two previous poses of `est`
+    (frame 0: ground truth; frame 1: the previous pose)."""
+    if i == 0:
+        return seq.poses[0].copy()
+    if i == 1:
+        return est[0].copy()
+    a, b = est[i - 2], est[i - 1]
+    ai = np.eye(4)
+    ai[:3, :3] = a[:3, :3].T
+    ai[:3, 3] = -a[:3, :3].T @ a[:3, 3]
+    return b @ (ai @ b)
+
+
+def run_oracle(seq, n_frames, r_max, max_it, conv, closed_loop=False):
+    """The FP64 oracle on the first n_frames frames with its own constant-velocity
+    recursion; returns (poses, seconds spent per frame, setup seconds)."""
+    from scipy.spatial import cKDTree
+
+    from oracle import covariance as oc
+    from oracle import gicp as og
+
+    t0 = time.perf_counter()
+    map_cov = oc.regularise6(seq.map_cov_raw, oc.REG_PLANE, 1e-3).astype(np.float32)
+    tree = cKDTree(seq.map_means.astype(np.float64))
+    setup = time.perf_counter() - t0
+    est, secs = [], []
+    for i in range(n_frames):
+        init = cv_init(seq, est if closed_loop else seq.poses, i)
+        t1 = time.perf_counter()
+        src = seq.frame(i)
+        cs = oc.covariances(src, 20, oc.REG_PLANE, 1e-3)
+        r = og.register(src, cs, seq.map_means, map_cov, init, r_max=r_max, max_it=max_it,
+                        conv_rot=conv, conv_trans=conv, tree=tree)
+        secs.append(time.perf_counter() - t1)
+        est.append(r.pose)
+    return est, secs, setup
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=95)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--map-size", type=int, default=1_000_000)
+    ap.add_argument("--cpu-frames", type=int, default=4, help="frames the CPU oracle baseline registers")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--closed-loop", action="store_true",
+                    help="initialise each frame from the previous estimates instead of the ground-truth poses")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (a batch of registrations "
+              "shards with no communication; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_12550_amd as g
+    import synth
+
+    g.lib()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    seq = synth.C2Sequence(n_frames=args.frames, map_size=args.map_size)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    seq.prefetch(range(args.frames), workers=workers)
+    npts = np.array([seq.frame(i).shape[0] for i in range(args.frames)])
+    log(f"workload generated in {time.perf_counter() - t0:.1f} s: {args.frames} frames, "
+        f"{npts.mean():.0f} pts/frame (min {npts.min()}, max {npts.max()}), map {args.map_size}")
+
+    ctx = g.Context(0)
+    means = g.to_soa(seq.map_means)
+    covs = g.to_soa(seq.map_cov_raw)
+    frames = [g.to_soa(seq.frame(i)) for i in range(args.frames)]
+    torch.cuda.synchronize()
+
+    # map: built once (static map), timed on its own
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    map_cell = ctx.estimate_cell(means, 8)
+    ev0.record()
+    gmap = ctx.map_build(means, covs, cell=map_cell, reg_mode=g.REG_PLANE, eps=1e-3)
+    ev1.record()
+    torch.cuda.synchronize()
+    map_ms = ev0.elapsed_time(ev1)
+    src_cell = ctx.estimate_cell(frames[0], 20)
+    log(f"map built in {map_ms:.2f} ms (cell {map_cell * 100:.2f} cm); source cell {src_cell * 100:.2f} cm")
+
+    r_max, max_it, conv = 0.1, 20, 1e-6
+    prm = g.params(k=20, eps=1e-3, r_max=r_max, max_it=max_it, conv_rot=conv, conv_trans=conv,
+                   reg_mode=g.REG_PLANE, cell_src=src_cell)
+    nf = args.frames
+    est = {}
+    iters = []
+    statuses = []
+
+    def step(s):
+        i = s % nf
+        if i == 0:
+            est.clear()
+        init = cv_init(seq, est if args.closed_loop else seq.poses, i)
+        r = ctx.register(frames[i], gmap, init, prm)
+        est[i] = r.pose
+        return r
+
+    for s in range(args.warmup):
+        step(s)
+    first_poses = {i: p.copy() for i, p in est.items()}
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t1 = time.perf_counter()
+    for s in range(args.warmup, args.warmup + args.steps):
+        r = step(s)
+        iters.append(r.iters)
+        statuses.append(r.status)
+        if (s % nf) < args.cpu_frames:
+            first_poses[s % nf] = r.pose.copy()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = {gid: ctx.profile_read(gid) for gid in range(4)}
+    fps = args.steps / elapsed
+    log(f"timed {args.steps} frames in {elapsed * 1e3:.1f} ms: {fps:.1f} frames/s, "
+        f"mean iterations {np.mean(iters):.2f}, statuses {sorted(set(statuses))}")
+
+    # ground-truth error (information only: the synthetic frames are noisy resamples)
+    gt_err = np.array([pose_delta(p, seq.poses[i]) for i, p in est.items()])
+
+    kernels = {}
+    for gid, (n, ms, units) in prof.items():
+        if n == 0:
+            continue
+        kernels[GROUP_NAMES[gid]] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms_per_frame": ms / args.steps,
+                                     "units_per_launch": units / n}
+    dom = max((gid for gid in prof if prof[gid][0] > 0 and gid in (0, 1)), key=lambda gid: prof[gid][1])
+    n, ms, units = prof[dom]
+    achieved = BYTES_PER_UNIT[dom] * units / (ms * 1e-3) / 1e9
+    roofline = {"kernel": GROUP_NAMES[dom], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "bytes_per_unit": BYTES_PER_UNIT[dom], "units_per_launch": units / n,
+                "avg_launch_us": 1e3 * ms / n}
+
+    cpu = None
+    err_vs_oracle = None
+    if not args.no_cpu_baseline and args.cpu_frames > 0:
+        nc = min(args.cpu_frames, nf)
+        opos, secs, setup = run_oracle(seq, nc, r_max, max_it, conv, args.closed_loop)
+        # the GPU poses of frames 0..nc-1 from its own recursion
+        gpu_first = [first_poses.get(i, est.get(i)) for i in range(nc)]
+        errs = np.array([pose_delta(gp, op) for gp, op in zip(gpu_first, opos)])
+        err_vs_oracle = {"frames": nc, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max())}
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": round(nc / sum(secs), 4), "unit": "frames/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {nc} frames of the same trajectory (own constant-velocity recursion), "
+                         f"FP64 numpy/scipy, cKDTree workers=-1; per-frame time excludes the one-off "
+                         f"map preparation ({setup:.1f} s: eigh of 1M covariances + kd-tree)"}
+        log(f"cpu oracle: {cpu['value']} frames/s over {nc} frames; GPU vs oracle max "
+            f"{err_vs_oracle['max_rad']:.2e} rad {err_vs_oracle['max_m']:.2e} m")
+
+    out = {
+        "metric": "G-ICP frames/s (60k pts vs 1M-Gaussian map) at pose err <=1e-4 vs FP64",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "frame-to-map tracking: 1200x680 depth frames voxelised at 2 cm "
+                               f"(mean {npts.mean():.0f} pts) vs a {args.map_size}-Gaussian map, "
+                               f"{nf}-frame trajectory, k=20, plane eps=1e-3, r_max=0.1 m, <=20 GN it",
+                   "frames": nf, "map_gaussians": args.map_size, "mean_points": float(npts.mean()),
+                   "form": "plain per-frame (one gicp_register call per frame)",
+                   "init": ("constant velocity from the previous two estimates" if args.closed_loop else
+                            "constant-velocity prediction from the previous two ground-truth poses")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "pose_err_vs_oracle": err_vs_oracle,
+        "pose_err_vs_ground_truth": {"mean_rad": float(gt_err[:, 0].mean()), "mean_m": float(gt_err[:, 1].mean())},
+        "mean_gn_iterations": float(np.mean(iters)),
+        "map_build_ms": round(map_ms, 3),
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+    gmap.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

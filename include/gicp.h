@@ -88,8 +88,25 @@ typedef struct gicp_params {
     int32_t reg_mode;       /* gicp_reg_mode for source covariances computed by the call */
     float cell_src;         /* grid cell [m] for the source k-NN; <= 0: estimate (synchronises) */
     int32_t precision;      /* gicp_precision */
-    int32_t reserved;
+    int32_t flags;          /* GICP_FLAG_* */
 } gicp_params;
+
+/* gicp_params.flags */
+enum {
+    /* Run each Gauss-Newton iteration as its own pair of kernel launches
+     * (linearise, then solve), max_it pairs per call, instead of the
+     * persistent work-queue kernel that runs every iteration in one launch. */
+    GICP_FLAG_MULTI_LAUNCH = 1
+};
+
+/* One problem of a batched registration. */
+typedef struct gicp_problem {
+    const float* src;       /* SoA [3][n] source points (device) */
+    const float* src_covs;  /* SoA [6][n] source covariances (device), or NULL: computed */
+    int64_t n;
+    const gicp_map* map;
+    double init_pose[16];   /* row-major 4x4 (host) */
+} gicp_problem;
 
 typedef struct gicp_stats {
     int32_t iters;          /* Gauss-Newton iterations run */
@@ -182,6 +199,19 @@ int gicp_register(gicp_ctx* ctx, const float* src, const float* src_covs, int64_
                   double pose[16], double H[36], double b[6], float* src_covs_out,
                   gicp_stats* stats, void* stream);
 
+/* Registers `nprob` independent problems in one persistent work-queue kernel
+ * (same method and parameters as gicp_register; problems may differ in size
+ * and map).  Work items are chunks of 256 source points of one problem at its
+ * current pose; the last chunk of an iteration runs that problem's FP64 solve
+ * and posts its next iteration, so problems advance independently and finish
+ * at their own iteration counts.  Outputs (host): poses [nprob][16],
+ * Hs [nprob][36], bs [nprob][6] (each nullable), stats [nprob] (nullable).
+ * Source covariances are computed first for problems whose src_covs is NULL.
+ * Synchronises the stream once.  Returns GICP_E_ARG for nprob outside
+ * [1, 4096] or an invalid problem; per-problem statuses are in stats. */
+int gicp_register_batch(gicp_ctx* ctx, int nprob, const gicp_problem* probs, const gicp_params* params,
+                        double* poses, double* Hs, double* bs, gicp_stats* stats, void* stream);
+
 /* The problem statement form: builds a transient map from (map_means,
  * map_covs, m) with cell size `map_cell` (<= 0: estimated) and no target
  * regularisation, registers, and destroys the map. */
@@ -189,6 +219,18 @@ int gicp_register_pair(gicp_ctx* ctx, const float* src, const float* src_covs, i
                        const float* map_means, const float* map_covs, int64_t m, float map_cell,
                        const double init_pose[16], const gicp_params* params,
                        double pose[16], double H[36], double b[6], gicp_stats* stats, void* stream);
+
+/* Kernel timing.  While enabled, the context brackets its kernels with HIP
+ * events on the stream they run on and accumulates, per kernel group, the
+ * number of launches that did work, their summed duration and the work units
+ * they processed.  Groups: 0 = correspondence + linearisation (unit: source
+ * point per iteration), 1 = fused k-NN + covariance (unit: point), 2 = grid
+ * build (cell keys, radix sort, cell table; unit: point), 3 = solve and update
+ * (unit: iteration).  Durations are collected when the context synchronises
+ * (gicp_register, gicp_sync_status).  gicp_profile(ctx, 1) enables and resets. */
+enum { GICP_PROF_LINEARIZE = 0, GICP_PROF_KNN_COV = 1, GICP_PROF_GRID = 2, GICP_PROF_SOLVE = 3, GICP_PROF_GROUPS = 4 };
+int gicp_profile(gicp_ctx* ctx, int enable);
+int gicp_profile_read(gicp_ctx* ctx, int group, int64_t* launches, double* total_ms, double* units);
 
 #ifdef __cplusplus
 }

@@ -107,14 +107,17 @@ def linearise(T, src, src_cov, tgt, tgt_cov, r_max, tree=None):
 
 
 def register(src, src_cov6, tgt, tgt_cov6, init, r_max=0.1, max_it=30,
-             conv_rot=0.0, conv_trans=0.0, keep_history=False) -> Result:
+             conv_rot=0.0, conv_trans=0.0, keep_history=False, tree=None) -> Result:
     """Gauss-Newton G-ICP.  Inputs are the FP32 arrays the GPU sees, read
-    exactly into FP64; covariances in the [n,6] layout."""
+    exactly into FP64; covariances in the [n,6] layout.  ``tree`` optionally
+    supplies a prebuilt kd-tree of ``tgt`` (for repeated registrations against
+    one map)."""
     src = np.asarray(src, np.float32).astype(np.float64)
     tgt = np.asarray(tgt, np.float32).astype(np.float64)
     Cs = from6(np.asarray(src_cov6, np.float32).astype(np.float64))
     Ct = from6(np.asarray(tgt_cov6, np.float32).astype(np.float64))
-    tree = cKDTree(tgt)
+    if tree is None:
+        tree = cKDTree(tgt)
     T = np.array(init, np.float64)
     H = np.zeros((6, 6))
     b = np.zeros(6)

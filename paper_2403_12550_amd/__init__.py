@@ -14,11 +14,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK, Params,
-                   Stats)
+from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_MULTI_LAUNCH, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK,
+                   Params, Problem, Stats)
 
-__all__ = ["Context", "Map", "Params", "Stats", "RegisterResult", "GicpError", "params",
-           "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "to_soa", "lib"]
+__all__ = ["Context", "Map", "Params", "Stats", "Problem", "RegisterResult", "GicpError", "params",
+           "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "FLAG_MULTI_LAUNCH",
+           "to_soa", "lib"]
 
 
 class GicpError(RuntimeError):
@@ -117,6 +118,22 @@ class Context:
         except Exception:
             pass
 
+    def profile(self, enable: bool = True):
+        """Enable (and reset) or disable the library's HIP-event kernel timing."""
+        st = lib().gicp_profile(self.handle, int(enable))
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_profile")
+
+    def profile_read(self, group: int):
+        """(launches that did work, summed milliseconds, work units) of a kernel group."""
+        n = C.c_int64()
+        ms = C.c_double()
+        u = C.c_double()
+        st = lib().gicp_profile_read(self.handle, group, C.byref(n), C.byref(ms), C.byref(u))
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_profile_read")
+        return int(n.value), float(ms.value), float(u.value)
+
     def sync_status(self) -> int:
         return lib().gicp_sync_status(self.handle, _stream())
 
@@ -185,3 +202,30 @@ class Context:
             raise GicpError(st, "gicp_register")
         return RegisterResult(np.array(pose[:]).reshape(4, 4), np.array(H[:]).reshape(6, 6), np.array(b[:]),
                               stats.iters, stats.n_inliers, stats.cost, bool(stats.converged), st)
+
+    def register_batch(self, problems, prm: Params | None = None):
+        """problems: sequence of (src [3,n], src_covs [6,n] or None, Map, init_pose 4x4).
+        Returns a list of RegisterResult (one per problem)."""
+        prm = prm or params()
+        k = len(problems)
+        arr = (Problem * k)()
+        for i, (src, scov, gmap, init) in enumerate(problems):
+            _check_f32_cuda(src, 3, "src")
+            if scov is not None:
+                _check_f32_cuda(scov, 6, "src_covs")
+            arr[i].src = _ptr(src)
+            arr[i].src_covs = _ptr(scov)
+            arr[i].n = src.shape[1]
+            arr[i].map = gmap.handle
+            arr[i].init_pose[:] = [float(v) for v in np.asarray(init, np.float64).reshape(16)]
+        poses = np.zeros((k, 16))
+        Hs = np.zeros((k, 36))
+        bs = np.zeros((k, 6))
+        stats = (Stats * k)()
+        st = lib().gicp_register_batch(self.handle, k, arr, C.byref(prm), poses.ctypes.data, Hs.ctypes.data,
+                                       bs.ctypes.data, stats, _stream())
+        if st in (_abi.GICP_E_ARG, _abi.GICP_E_HIP, _abi.GICP_E_OOM):
+            raise GicpError(st, "gicp_register_batch")
+        return [RegisterResult(poses[i].reshape(4, 4), Hs[i].reshape(6, 6), bs[i], stats[i].iters,
+                               stats[i].n_inliers, stats[i].cost, bool(stats[i].converged), stats[i].status)
+                for i in range(k)]

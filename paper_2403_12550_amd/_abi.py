@@ -24,7 +24,20 @@ class Params(C.Structure):
         ("reg_mode", C.c_int32),
         ("cell_src", C.c_float),
         ("precision", C.c_int32),
-        ("reserved", C.c_int32),
+        ("flags", C.c_int32),
+    ]
+
+
+FLAG_MULTI_LAUNCH = 1
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("src", C.c_void_p),
+        ("src_covs", C.c_void_p),
+        ("n", C.c_int64),
+        ("map", C.c_void_p),
+        ("init_pose", C.c_double * 16),
     ]
 
 
@@ -63,7 +76,13 @@ SIGNATURES = {
                                 C.POINTER(Stats), P]),
     "gicp_register_pair": (C.c_int, [P, P, P, I64, P, P, I64, C.c_float, D16, C.POINTER(Params), D16, D36,
                                      D6, C.POINTER(Stats), P]),
+    "gicp_register_batch": (C.c_int, [P, C.c_int, C.POINTER(Problem), C.POINTER(Params), P, P, P,
+                                      C.POINTER(Stats), P]),
+    "gicp_profile": (C.c_int, [P, C.c_int]),
+    "gicp_profile_read": (C.c_int, [P, C.c_int, C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
+
+PROF_LINEARIZE, PROF_KNN_COV, PROF_GRID, PROF_SOLVE = 0, 1, 2, 3
 
 _lib = None
 

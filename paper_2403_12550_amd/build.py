@@ -23,6 +23,9 @@ FLAGS = [
     "-shared",
     # packed FP32 instructions stay off (the compiler would otherwise form them)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse multiply-adds only within one expression, so that the same source
+    # expression rounds the same way in every kernel that inlines it
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
 ]

@@ -59,15 +59,37 @@ uint32_t table_capacity(int64_t n) {
 
 }  // namespace
 
+struct ProfMark {
+    int group;
+    hipEvent_t a, b;
+    double units;
+    int iter;   // Gauss-Newton iteration index (-1: not an iteration)
+};
+
 struct gicp_ctx {
     int device = 0;
     int* d_err = nullptr;
     int* h_err = nullptr;
     GridBufs grid;
     Buf covs, partials, kth;
-    RegState* d_state = nullptr;
-    RegState* h_state = nullptr;
+    RegState* d_state = nullptr;     // [state_cap]
+    RegState* h_state = nullptr;     // pinned [state_cap]
+    ProbDev* d_probs = nullptr;      // [state_cap]
+    ProbDev* h_probs = nullptr;      // pinned [state_cap]
+    int state_cap = 0;
+    QueueDev* d_queue = nullptr;
+    Buf items, arrive;
+    int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
+    double queue_units = 0.0;        // source points x iterations of the last queue launch
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<ProfMark> marks;
+    int64_t launches[GICP_PROF_GROUPS] = {0, 0, 0, 0};
+    double ms[GICP_PROF_GROUPS] = {0, 0, 0, 0};
+    double units[GICP_PROF_GROUPS] = {0, 0, 0, 0};
 };
 
 struct gicp_map {
@@ -84,6 +106,55 @@ namespace {
 
 int status_of(const HipError& e) { return e.e == hipErrorOutOfMemory ? GICP_E_OOM : GICP_E_HIP; }
 
+hipEvent_t next_event(gicp_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        check(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// Opens a timed region on stream s (no-op unless profiling); returns its mark index.
+int prof_open(gicp_ctx* c, int group, double units, int iter, hipStream_t s) {
+    if (!c->prof) return -1;
+    ProfMark m{group, next_event(c), next_event(c), units, iter};
+    check(hipEventRecord(m.a, s));
+    c->marks.push_back(m);
+    return (int)c->marks.size() - 1;
+}
+
+void prof_close(gicp_ctx* c, int mark, hipStream_t s) {
+    if (mark < 0) return;
+    check(hipEventRecord(c->marks[mark].b, s));
+}
+
+// After a synchronisation: accumulate the marks; iterations at or beyond
+// `iters_done` were launched but returned at once (converged) and are skipped.
+void prof_collect(gicp_ctx* c, int iters_done) {
+    for (const ProfMark& m : c->marks) {
+        if (m.iter >= 0 && m.iter >= iters_done) continue;
+        float ms = 0.f;
+        check(hipEventSynchronize(m.b));
+        check(hipEventElapsedTime(&ms, m.a, m.b));
+        c->launches[m.group] += 1;
+        c->ms[m.group] += ms;
+        c->units[m.group] += (m.iter == -2) ? c->queue_units : m.units;
+    }
+    c->marks.clear();
+    c->ev_used = 0;
+}
+
+void reserve_grid(GridBufs& gb, int64_t n) {
+    ensure<uint32_t>(gb.keys_a, n);
+    ensure<uint32_t>(gb.vals_a, n);
+    ensure<uint32_t>(gb.keys_b, n);
+    ensure<uint32_t>(gb.vals_b, n);
+    ensure<uint8_t>(gb.scratch, radix_scratch_bytes(n));
+    ensure<float4>(gb.spts, n);
+    ensure<uint4>(gb.table, table_capacity(n));
+}
+
 // Builds the cell grid of n points (SoA, row stride `stride`) into `gb`.
 GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const float* xyz, int64_t n, int64_t stride, float h,
                     hipStream_t s, float4* spts_out = nullptr, uint4* table_out = nullptr,
@@ -97,11 +168,13 @@ GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const float* xyz, int64_t n, in
     float4* spts = spts_out ? spts_out : ensure<float4>(gb.spts, n);
     uint4* table = table_out ? table_out : ensure<uint4>(gb.table, cap);
     const float inv_h = 1.0f / h;
+    const int pm = prof_open(ctx, GICP_PROF_GRID, (double)n, -1, s);
     check(launch_cell_keys(xyz, n, stride, inv_h, ka, va, ctx->d_err, s));
     check(radix_sort_30(ka, va, kb, vb, n, scr, s));
     check(launch_table_clear(table, cap, s));
-    check(launch_table_build(kb, vb, n, xyz, stride, spts, table, cap - 1, s));
-    if (svals_keep) check(hipMemcpyAsync(svals_keep, vb, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    check(launch_table_build(ka, va, n, xyz, stride, spts, table, cap - 1, s));
+    prof_close(ctx, pm, s);
+    if (svals_keep) check(hipMemcpyAsync(svals_keep, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     GridView g;
     g.spts = spts;
     g.table = table;
@@ -123,6 +196,25 @@ float estimate_cell(gicp_ctx* ctx, const float* xyz, int64_t n, int k, hipStream
     float c = v[(size_t)(0.75 * (ns - 1))] * 1.1f;
     if (!(c > 1e-6f) || !std::isfinite(c)) c = 1e-3f;
     return c;
+}
+
+void ensure_states(gicp_ctx* c, int n) {
+    if (n <= c->state_cap) return;
+    const int cap = std::max(n, 2 * c->state_cap);
+    if (c->d_state) check(hipFree(c->d_state));
+    if (c->h_state) check(hipHostFree(c->h_state));
+    if (c->d_probs) check(hipFree(c->d_probs));
+    if (c->h_probs) check(hipHostFree(c->h_probs));
+    c->d_state = nullptr;
+    c->h_state = nullptr;
+    c->d_probs = nullptr;
+    c->h_probs = nullptr;
+    c->state_cap = 0;
+    check(hipMalloc(&c->d_state, cap * sizeof(RegState)));
+    check(hipHostMalloc(&c->h_state, cap * sizeof(RegState)));
+    check(hipMalloc(&c->d_probs, cap * sizeof(ProbDev)));
+    check(hipHostMalloc(&c->h_probs, cap * sizeof(ProbDev)));
+    c->state_cap = cap;
 }
 
 bool valid_k(int k) { return k >= 1 && k <= 64; }
@@ -172,8 +264,7 @@ int gicp_create(gicp_ctx** out, int device) {
         check(hipSetDevice(device));
         check(hipMalloc(&c->d_err, 256));
         check(hipMemset(c->d_err, 0, 256));
-        check(hipMalloc(&c->d_state, sizeof(RegState)));
-        check(hipHostMalloc(&c->h_state, sizeof(RegState)));
+        check(hipMalloc(&c->d_queue, sizeof(QueueDev)));
         check(hipHostMalloc(&c->h_err, 256));
         check(hipHostMalloc(&c->h_kth, 256 * sizeof(float)));
         *out = c;
@@ -194,8 +285,14 @@ int gicp_destroy(gicp_ctx* c) {
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->d_state) (void)hipFree(c->d_state);
     if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->d_probs) (void)hipFree(c->d_probs);
+    if (c->h_probs) (void)hipHostFree(c->h_probs);
+    if (c->d_queue) (void)hipFree(c->d_queue);
+    release(c->items);
+    release(c->arrive);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_kth) (void)hipHostFree(c->h_kth);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return GICP_OK;
 }
@@ -207,6 +304,7 @@ int gicp_sync_status(gicp_ctx* c, void* stream) {
         hipStream_t s = (hipStream_t)stream;
         check(hipMemcpyAsync(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
         check(hipStreamSynchronize(s));
+        if (c->prof) prof_collect(c, 0);
         const int e = *c->h_err;
         if (e) check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
         check(hipStreamSynchronize(s));
@@ -254,7 +352,9 @@ int gicp_covariances(gicp_ctx* c, const float* pts, int64_t n, int k, float cell
         hipStream_t s = (hipStream_t)stream;
         const float h = cell > 0.f ? cell : estimate_cell(c, pts, n, k, s);
         GridView g = build_grid(c, c->grid, pts, n, n, h, s);
+        const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)n, -1, s);
         check(launch_knn_cov(g, pts, n, k, reg_mode, eps, covs, c->d_err, s));
+        prof_close(c, pm, s);
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);
@@ -280,8 +380,8 @@ int gicp_map_build(gicp_ctx* c, const float* means, const float* covs, int64_t m
         check(hipMalloc(&mp->table, (size_t)cap * sizeof(uint4)));
         check(hipMalloc(&mp->scov, 2 * m * sizeof(float4)));
         build_grid(c, c->grid, means, m, m, h, s, mp->spts, mp->table);
-        // the sorted values (original indices) are still in grid.vals_b
-        check(launch_map_covs(static_cast<const uint32_t*>(c->grid.vals_b.p), m, covs, m, reg_mode, eps, mp->scov,
+        // the sorted values (original indices) are still in grid.vals_a
+        check(launch_map_covs(static_cast<const uint32_t*>(c->grid.vals_a.p), m, covs, m, reg_mode, eps, mp->scov,
                               c->d_err, s));
         *out = mp;
         return GICP_OK;
@@ -309,6 +409,181 @@ int gicp_map_info(const gicp_map* mp, int64_t* m, float* cell) {
     return GICP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+MapView map_view(const gicp_map* map, const gicp_params* prm) {
+    MapView mv;
+    mv.g.spts = map->spts;
+    mv.g.table = map->table;
+    mv.g.mask = map->mask;
+    mv.g.n = (int32_t)map->m;
+    mv.g.h = map->h;
+    mv.g.inv_h = 1.0f / map->h;
+    mv.scov = map->scov;
+    mv.r_max = prm->r_max;
+    mv.r_max2 = prm->r_max * prm->r_max;
+    return mv;
+}
+
+bool valid_params(const gicp_params* prm) {
+    return prm && prm->max_it >= 0 && prm->r_max > 0.f && prm->precision >= 0 && prm->precision <= 2;
+}
+
+// Registers nprob problems (validated by the caller).  covs_out[p] (nullable)
+// receives problem p's source covariances when the call computes them.
+// Returns the per-problem statuses in stats (never null here).
+void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm,
+                   float* const* covs_out, double* poses, double* Hs, double* bs, gicp_stats* stats, hipStream_t s) {
+    // 1. source covariances where missing
+    int64_t need = 0;
+    for (int p = 0; p < nprob; ++p)
+        if (!probs[p].src_covs && !(covs_out && covs_out[p])) need += 6 * probs[p].n;
+    float* wcov = need ? ensure<float>(c->covs, need) : nullptr;
+    // size the grid workspace for the largest source up front (a reallocation
+    // between problems would synchronise the device)
+    int64_t nmax = 0;
+    for (int p = 0; p < nprob; ++p)
+        if (!probs[p].src_covs) nmax = std::max<int64_t>(nmax, probs[p].n);
+    if (nmax > 0) reserve_grid(c->grid, nmax);
+    std::vector<const float*> scov(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        const gicp_problem& P = probs[p];
+        float* out = covs_out ? covs_out[p] : nullptr;
+        if (P.src_covs) {
+            scov[p] = P.src_covs;
+            if (out && out != P.src_covs)
+                check(hipMemcpyAsync(out, P.src_covs, 6 * P.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+            continue;
+        }
+        float* dst = out;
+        if (!dst) {
+            dst = wcov;
+            wcov += 6 * P.n;
+        }
+        const float h = prm->cell_src > 0.f ? prm->cell_src : estimate_cell(c, P.src, P.n, prm->k, s);
+        GridView g = build_grid(c, c->grid, P.src, P.n, P.n, h, s);
+        const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)P.n, -1, s);
+        check(launch_knn_cov(g, P.src, P.n, prm->k, prm->reg_mode, prm->eps, dst, c->d_err, s));
+        prof_close(c, pm, s);
+        scov[p] = dst;
+    }
+    // 2. states and problem descriptors
+    ensure_states(c, nprob);
+    int64_t chunks = 0;
+    for (int p = 0; p < nprob; ++p) {
+        const gicp_problem& P = probs[p];
+        RegState& hs = c->h_state[p];
+        std::memset(&hs, 0, sizeof(RegState));
+        for (int i = 0; i < 16; ++i) hs.pose[i] = P.init_pose[i];
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) hs.Rf[3 * i + j] = (float)P.init_pose[4 * i + j];
+            hs.tf[i] = (float)P.init_pose[4 * i + 3];
+        }
+        hs.max_it = prm->max_it;
+        hs.done = prm->max_it <= 0 ? 1 : 0;
+        hs.conv_rot = prm->conv_rot;
+        hs.conv_trans = prm->conv_trans;
+        hs.acc = prm->precision;
+        ProbDev& pd = c->h_probs[p];
+        pd.src = P.src;
+        pd.scov = scov[p];
+        pd.n = P.n;
+        pd.nchunks = (int32_t)((P.n + kChunk - 1) / kChunk);
+        pd.part0 = (int32_t)chunks;
+        pd.map = map_view(P.map, prm);
+        pd.st = c->d_state + p;
+        chunks += pd.nchunks;
+    }
+    check(hipMemcpyAsync(c->d_state, c->h_state, nprob * sizeof(RegState), hipMemcpyHostToDevice, s));
+    // 3. Gauss-Newton
+    if (prm->max_it > 0) {
+        if (prm->flags & GICP_FLAG_MULTI_LAUNCH) {
+            for (int p = 0; p < nprob; ++p) {
+                const ProbDev& pd = c->h_probs[p];
+                const int nb = gn_blocks(pd.n);
+                double* part = ensure<double>(c->partials, (size_t)nb * kNumAcc);
+                for (int it = 0; it < prm->max_it; ++it) {
+                    const int pl = prof_open(c, GICP_PROF_LINEARIZE, (double)pd.n, nprob == 1 ? it : -3, s);
+                    check(launch_gn_linearize(pd.src, pd.scov, pd.n, pd.map, pd.st, part, nb, prm->precision, s));
+                    prof_close(c, pl, s);
+                    const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, nprob == 1 ? it : -3, s);
+                    check(launch_gn_solve(part, nb, pd.st, s));
+                    prof_close(c, ps, s);
+                }
+            }
+        } else {
+            check(hipMemcpyAsync(c->d_probs, c->h_probs, nprob * sizeof(ProbDev), hipMemcpyHostToDevice, s));
+            const uint64_t cap64 = (uint64_t)chunks * (uint64_t)prm->max_it;
+            if (cap64 >= (1ull << 31)) throw HipError{hipErrorInvalidValue};
+            const uint32_t cap = (uint32_t)cap64;
+            uint32_t* items = ensure<uint32_t>(c->items, cap);
+            uint32_t* arrive = ensure<uint32_t>(c->arrive, nprob);
+            double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
+            const int acc = prm->precision;
+            if (!c->queue_workers[acc]) c->queue_workers[acc] = gn_queue_workers(acc);
+            const int workers = (int)std::min<int64_t>(chunks, c->queue_workers[acc]);
+            const int pq = prof_open(c, GICP_PROF_LINEARIZE, 0.0, -2, s);
+            check(launch_gn_queue(c->d_probs, nprob, c->d_queue, items, cap, (uint32_t)chunks, arrive, part, workers,
+                                  acc, s));
+            prof_close(c, pq, s);
+        }
+    }
+    check(hipMemcpyAsync(c->h_state, c->d_state, nprob * sizeof(RegState), hipMemcpyDeviceToHost, s));
+    check(hipMemcpyAsync(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    check(hipMemcpyAsync(c->h_err + 1, &c->d_queue->error, sizeof(int), hipMemcpyDeviceToHost, s));
+    check(hipStreamSynchronize(s));
+    double units = 0.0;
+    int iters0 = c->h_state[0].iters;
+    for (int p = 0; p < nprob; ++p) units += (double)probs[p].n * c->h_state[p].iters;
+    c->queue_units = units;
+    if (c->prof) prof_collect(c, nprob == 1 ? iters0 : 1 << 30);
+    const bool nonfinite = (c->h_err[0] & kErrNonFinite) != 0;
+    const bool qerr = !(prm->flags & GICP_FLAG_MULTI_LAUNCH) && prm->max_it > 0 && c->h_err[1] != 0;
+    if (nonfinite) {
+        check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
+        check(hipStreamSynchronize(s));
+    }
+    for (int p = 0; p < nprob; ++p) {
+        const RegState& hs = c->h_state[p];
+        if (poses)
+            for (int i = 0; i < 16; ++i) poses[16 * p + i] = hs.pose[i];
+        if (Hs) {
+            int q = 0;
+            for (int i = 0; i < 6; ++i)
+                for (int j = i; j < 6; ++j) {
+                    Hs[36 * p + 6 * i + j] = hs.H[q];
+                    Hs[36 * p + 6 * j + i] = hs.H[q];
+                    ++q;
+                }
+        }
+        if (bs)
+            for (int i = 0; i < 6; ++i) bs[6 * p + i] = hs.b[i];
+        gicp_stats& st = stats[p];
+        st.iters = hs.iters;
+        st.n_inliers = (int32_t)hs.n_inl;
+        st.cost = hs.cost;
+        st.converged = hs.converged;
+        st.status = nonfinite ? GICP_E_NONFINITE : qerr ? GICP_E_HIP : hs.status;
+        st.hip_error = 0;
+    }
+}
+
+int fail(gicp_stats* stats, int nprob, const HipError& e) {
+    const int st = status_of(e);
+    if (stats)
+        for (int p = 0; p < nprob; ++p) {
+            stats[p].status = st;
+            stats[p].hip_error = (int32_t)e.e;
+        }
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gicp_register(gicp_ctx* c, const float* src, const float* src_covs, int64_t n, const gicp_map* map,
                   const double init_pose[16], const gicp_params* prm, double pose[16], double H[36], double b[6],
                   float* src_covs_out, gicp_stats* stats, void* stream) {
@@ -316,82 +591,48 @@ int gicp_register(gicp_ctx* c, const float* src, const float* src_covs, int64_t 
     if (!c || !src || !map || !init_pose || !prm || !pose || !H || !b || n < 1 || n >= (1ll << 31))
         return GICP_E_ARG;
     if (!src_covs && (!valid_k(prm->k) || n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
-    if (prm->max_it < 0 || !(prm->r_max > 0.f)) return GICP_E_ARG;
-    if (prm->precision < 0 || prm->precision > 2) return GICP_E_ARG;
-    int status = GICP_OK;
+    if (!valid_params(prm)) return GICP_E_ARG;
+    if ((n + kChunk - 1) / kChunk >= (1ll << kChunkBits)) return GICP_E_ARG;
+    gicp_problem P;
+    P.src = src;
+    P.src_covs = src_covs;
+    P.n = n;
+    P.map = map;
+    for (int i = 0; i < 16; ++i) P.init_pose[i] = init_pose[i];
+    gicp_stats st;
+    std::memset(&st, 0, sizeof(st));
+    float* outs[1] = {src_covs_out};
     try {
         check(hipSetDevice(c->device));
-        hipStream_t s = (hipStream_t)stream;
-        const float* scov = src_covs;
-        if (!scov) {
-            float* dst = src_covs_out ? src_covs_out : ensure<float>(c->covs, 6 * n);
-            const float h = prm->cell_src > 0.f ? prm->cell_src : estimate_cell(c, src, n, prm->k, s);
-            GridView g = build_grid(c, c->grid, src, n, n, h, s);
-            check(launch_knn_cov(g, src, n, prm->k, prm->reg_mode, prm->eps, dst, c->d_err, s));
-            scov = dst;
-        } else if (src_covs_out && src_covs_out != src_covs) {
-            check(hipMemcpyAsync(src_covs_out, src_covs, 6 * n * sizeof(float), hipMemcpyDeviceToDevice, s));
-        }
-        RegState* hs = c->h_state;
-        std::memset(hs, 0, sizeof(RegState));
-        for (int i = 0; i < 16; ++i) hs->pose[i] = init_pose[i];
-        for (int i = 0; i < 3; ++i) {
-            for (int j = 0; j < 3; ++j) hs->Rf[3 * i + j] = (float)init_pose[4 * i + j];
-            hs->tf[i] = (float)init_pose[4 * i + 3];
-        }
-        hs->max_it = prm->max_it;
-        hs->done = prm->max_it <= 0 ? 1 : 0;
-        hs->conv_rot = prm->conv_rot;
-        hs->conv_trans = prm->conv_trans;
-        hs->acc = prm->precision;
-        check(hipMemcpyAsync(c->d_state, hs, sizeof(RegState), hipMemcpyHostToDevice, s));
-        MapView mv;
-        mv.g.spts = map->spts;
-        mv.g.table = map->table;
-        mv.g.mask = map->mask;
-        mv.g.n = (int32_t)map->m;
-        mv.g.h = map->h;
-        mv.g.inv_h = 1.0f / map->h;
-        mv.scov = map->scov;
-        mv.r_max = prm->r_max;
-        mv.r_max2 = prm->r_max * prm->r_max;
-        const int nb = gn_blocks(n);
-        double* part = ensure<double>(c->partials, (size_t)nb * kNumAcc);
-        for (int it = 0; it < prm->max_it; ++it)
-            check(launch_gn_iteration(src, scov, n, mv, c->d_state, part, nb, prm->precision, s));
-        check(hipMemcpyAsync(hs, c->d_state, sizeof(RegState), hipMemcpyDeviceToHost, s));
-        check(hipMemcpyAsync(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
-        check(hipStreamSynchronize(s));
-        for (int i = 0; i < 16; ++i) pose[i] = hs->pose[i];
-        int q = 0;
-        for (int i = 0; i < 6; ++i)
-            for (int j = i; j < 6; ++j) {
-                H[6 * i + j] = hs->H[q];
-                H[6 * j + i] = hs->H[q];
-                ++q;
-            }
-        for (int i = 0; i < 6; ++i) b[i] = hs->b[i];
-        status = hs->status;
-        if (*c->h_err & kErrNonFinite) {
-            status = GICP_E_NONFINITE;
-            check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
-            check(hipStreamSynchronize(s));
-        }
-        if (stats) {
-            stats->iters = hs->iters;
-            stats->n_inliers = (int32_t)hs->n_inl;
-            stats->cost = hs->cost;
-            stats->converged = hs->converged;
-            stats->status = status;
-        }
-        return status;
+        register_many(c, 1, &P, prm, outs, pose, H, b, &st, (hipStream_t)stream);
     } catch (const HipError& e) {
-        if (stats) {
-            stats->status = status_of(e);
-            stats->hip_error = (int32_t)e.e;
-        }
-        return status_of(e);
+        return fail(stats, 1, e);
     }
+    if (stats) *stats = st;
+    return st.status;
+}
+
+int gicp_register_batch(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm, double* poses,
+                        double* Hs, double* bs, gicp_stats* stats, void* stream) {
+    if (stats) std::memset(stats, 0, (size_t)std::max(nprob, 0) * sizeof(gicp_stats));
+    if (!c || !probs || nprob < 1 || nprob > kMaxProblems || !valid_params(prm)) return GICP_E_ARG;
+    for (int p = 0; p < nprob; ++p) {
+        const gicp_problem& P = probs[p];
+        if (!P.src || !P.map || P.n < 1 || P.n >= (1ll << 31)) return GICP_E_ARG;
+        if ((P.n + kChunk - 1) / kChunk >= (1ll << kChunkBits)) return GICP_E_ARG;
+        if (!P.src_covs && (!valid_k(prm->k) || P.n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
+    }
+    std::vector<gicp_stats> st(nprob);
+    try {
+        check(hipSetDevice(c->device));
+        register_many(c, nprob, probs, prm, nullptr, poses, Hs, bs, st.data(), (hipStream_t)stream);
+    } catch (const HipError& e) {
+        return fail(stats, nprob, e);
+    }
+    if (stats) std::memcpy(stats, st.data(), nprob * sizeof(gicp_stats));
+    for (int p = 0; p < nprob; ++p)
+        if (st[p].status == GICP_E_HIP || st[p].status == GICP_E_NONFINITE) return st[p].status;
+    return GICP_OK;
 }
 
 int gicp_register_pair(gicp_ctx* c, const float* src, const float* src_covs, int64_t n, const float* map_means,
@@ -404,6 +645,33 @@ int gicp_register_pair(gicp_ctx* c, const float* src, const float* src_covs, int
     st = gicp_register(c, src, src_covs, n, mp, init_pose, prm, pose, H, b, nullptr, stats, stream);
     gicp_map_destroy(mp);
     return st;
+}
+
+int gicp_profile(gicp_ctx* c, int enable) {
+    if (!c) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        check(hipDeviceSynchronize());
+        c->prof = enable != 0;
+        c->marks.clear();
+        c->ev_used = 0;
+        for (int g = 0; g < GICP_PROF_GROUPS; ++g) {
+            c->launches[g] = 0;
+            c->ms[g] = 0.0;
+            c->units[g] = 0.0;
+        }
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_profile_read(gicp_ctx* c, int group, int64_t* launches, double* total_ms, double* units) {
+    if (!c || group < 0 || group >= GICP_PROF_GROUPS) return GICP_E_ARG;
+    if (launches) *launches = c->launches[group];
+    if (total_ms) *total_ms = c->ms[group];
+    if (units) *units = c->units[group];
+    return GICP_OK;
 }
 
 }  // extern "C"

@@ -98,4 +98,38 @@ __device__ __forceinline__ float block_clearance(float qx, float qy, float qz, C
     return d;
 }
 
+// Slack of the cell assignment: a point assigned to cell c by floor(p * inv_h)
+// lies within [c*h - slack, (c+1)*h + slack] per axis.
+__device__ __forceinline__ float cell_slack(float qx, float qy, float qz, int R, float h) {
+    const float mag = fmaxf(fmaxf(fabsf(qx), fabsf(qy)), fabsf(qz)) + (float)(R + 1) * h;
+    return 4e-6f * mag + 1e-6f * h;
+}
+
+// Lower bound of the squared distance from q to any point assigned to cell
+// (cx, cy, cz): the distance to the cell box grown by the slack.
+__device__ __forceinline__ float cell_lower_bound2(float qx, float qy, float qz, int cx, int cy, int cz, float h,
+                                                  float slack) {
+    const float dx = fmaxf(fmaxf((float)cx * h - slack - qx, qx - (float)(cx + 1) * h - slack), 0.f);
+    const float dy = fmaxf(fmaxf((float)cy * h - slack - qy, qy - (float)(cy + 1) * h - slack), 0.f);
+    const float dz = fmaxf(fmaxf((float)cz * h - slack - qz, qz - (float)(cz + 1) * h - slack), 0.f);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// A cell whose lower bound exceeds the current k-th key cannot hold a point
+// that ranks before it (the FP32 key is within 3e-7 relative of the exact
+// squared distance; the factor covers that and the rounding of the bound).
+__device__ __forceinline__ bool cell_pruned(float lb2, float kth_key) { return lb2 * (1.f - 2e-6f) > kth_key; }
+
+// The 27 offsets of the block around a cell, nearest first: the cell itself,
+// 6 faces, 12 edges, 8 corners.  Offset j is packed in 5 bits as
+// (dx+1) + 3(dy+1) + 9(dz+1), twelve to a 64-bit word (pure ALU; j is
+// uniform across the wavefront).
+__device__ __forceinline__ void block_offset(int j, int& dx, int& dy, int& dz) {
+    const uint64_t w = (j < 12) ? 0x01c5eb4d8905398dull : (j < 24) ? 0x0920c2066670dea5ull : 0x0000000000006b14ull;
+    const int o = (int)((w >> (5 * (j % 12))) & 31u);
+    dx = o % 3 - 1;
+    dy = (o / 3) % 3 - 1;
+    dz = o / 9 - 1;
+}
+
 }  // namespace gicp

@@ -43,6 +43,7 @@ struct Acc<GICP_ACC_TWOSUM> {
         s[j] = t;
         c[j] += e;
     }
+    __device__ __forceinline__ void put(int j, float x) { s[j] = x; }
     __device__ __forceinline__ void wave_reduce() {
 #pragma unroll
         for (int j = 0; j < kNumAcc; ++j) {
@@ -68,6 +69,7 @@ struct Acc<GICP_ACC_FP32> {
         for (int j = 0; j < kNumAcc; ++j) s[j] = 0.f;
     }
     __device__ __forceinline__ void add(int j, float x) { s[j] += x; }
+    __device__ __forceinline__ void put(int j, float x) { s[j] = x; }
     __device__ __forceinline__ void wave_reduce() {
 #pragma unroll
         for (int j = 0; j < kNumAcc; ++j)
@@ -85,6 +87,7 @@ struct Acc<GICP_ACC_FP64> {
         for (int j = 0; j < kNumAcc; ++j) s[j] = 0.0;
     }
     __device__ __forceinline__ void add(int j, float x) { s[j] += (double)x; }
+    __device__ __forceinline__ void put(int j, float x) { s[j] = (double)x; }
     __device__ __forceinline__ void wave_reduce() {
 #pragma unroll
         for (int j = 0; j < kNumAcc; ++j)
@@ -95,13 +98,22 @@ struct Acc<GICP_ACC_FP64> {
 };
 
 // Exact 1-NN of q among the map means within the gate; returns the sorted
-// position (or -1).  Ranking by (FP32 key, original index).
+// position (or -1).  Ranking by (FP32 key, original index).  Cells are
+// visited nearest first and skipped when their distance lower bound exceeds
+// the best key so far (or the gate).
 __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz) {
     const GridView& g = m.g;
+    if (!finite3(qx, qy, qz)) return -1;
     uint64_t best = ~0ull;
     int32_t pos = -1;
     const Cell c = cell_of(qx, qy, qz, g.inv_h);
+    const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
+    auto bound = [&]() {
+        return fminf(best == ~0ull ? FLT_MAX : __uint_as_float((uint32_t)(best >> 32)), m.r_max2);
+    };
     auto scan = [&](int cx, int cy, int cz) {
+        const float lb = cell_lower_bound2(qx, qy, qz, cx, cy, cz, g.h, slack);
+        if (cell_pruned(lb, bound())) return;
         uint32_t start = 0;
         const uint32_t cnt = cell_lookup(g.table, g.mask, cell_key(cx, cy, cz), start);
         for (uint32_t j = 0; j < cnt; ++j) {
@@ -114,12 +126,13 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             }
         }
     };
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) scan(c.x + dx, c.y + dy, c.z + dz);
+    for (int j = 0; j < 27; ++j) {
+        int dx, dy, dz;
+        block_offset(j, dx, dy, dz);
+        scan(c.x + dx, c.y + dy, c.z + dz);
+    }
     const float r_gate = m.r_max * 1.000001f + 1e-6f;
-    bool done = false;
-    for (int R = 1; !done; ++R) {
+    for (int R = 1;; ++R) {
         const float clr = block_clearance(qx, qy, qz, c, R, g.h);
         if (clr > 0.f) {
             if (clr >= r_gate) break;
@@ -140,7 +153,6 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                     pos = j;
                 }
             }
-            done = true;
             break;
         }
         const int S = R + 1;
@@ -154,94 +166,91 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
     return (bk <= m.r_max2) ? pos : -1;
 }
 
-template <int ACC>
-__global__ __launch_bounds__(kBlock) void k_gn_linearize(const float* __restrict__ src,
-                                                         const float* __restrict__ scov, int64_t n, MapView map,
-                                                         const RegState* __restrict__ st,
-                                                         double* __restrict__ partials) {
-    if (st->done) return;
-    float R[9], t[3];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
+// Linearisation of one source point at the pose (R, t), accumulated into acc
+// (PUT: the lane's first and only point, stored instead of added).
+template <int ACC, bool PUT = false>
+__device__ __forceinline__ void linearize_point(const float* __restrict__ src, const float* __restrict__ scov,
+                                                int64_t n, int64_t i, const MapView& map, const float* R,
+                                                const float* t, Acc<ACC>& acc) {
+#define ACC_ADD(j, x) (PUT ? acc.put((j), (x)) : acc.add((j), (x)))
+    const float x = src[i], y = src[n + i], z = src[2 * n + i];
+    const float qx = R[0] * x + R[1] * y + R[2] * z + t[0];
+    const float qy = R[3] * x + R[4] * y + R[5] * z + t[1];
+    const float qz = R[6] * x + R[7] * y + R[8] * z + t[2];
+    const int32_t pos = nearest(map, qx, qy, qz);
+    if (pos < 0) return;
+    const float4 mu = map.g.spts[pos];
+    const float4 ca = map.scov[2 * pos];
+    const float4 cb = map.scov[2 * pos + 1];
+    // source covariance rotated: A = R Cs, S = A R^T
+    const float c00 = scov[i], c01 = scov[n + i], c02 = scov[2 * n + i];
+    const float c11 = scov[3 * n + i], c12 = scov[4 * n + i], c22 = scov[5 * n + i];
+    const float a00 = R[0] * c00 + R[1] * c01 + R[2] * c02;
+    const float a01 = R[0] * c01 + R[1] * c11 + R[2] * c12;
+    const float a02 = R[0] * c02 + R[1] * c12 + R[2] * c22;
+    const float a10 = R[3] * c00 + R[4] * c01 + R[5] * c02;
+    const float a11 = R[3] * c01 + R[4] * c11 + R[5] * c12;
+    const float a12 = R[3] * c02 + R[4] * c12 + R[5] * c22;
+    const float a20 = R[6] * c00 + R[7] * c01 + R[8] * c02;
+    const float a21 = R[6] * c01 + R[7] * c11 + R[8] * c12;
+    const float a22 = R[6] * c02 + R[7] * c12 + R[8] * c22;
+    const float s00 = ca.x + a00 * R[0] + a01 * R[1] + a02 * R[2];
+    const float s01 = ca.y + a00 * R[3] + a01 * R[4] + a02 * R[5];
+    const float s02 = ca.z + a00 * R[6] + a01 * R[7] + a02 * R[8];
+    const float s11 = ca.w + a10 * R[3] + a11 * R[4] + a12 * R[5];
+    const float s12 = cb.x + a10 * R[6] + a11 * R[7] + a12 * R[8];
+    const float s22 = cb.y + a20 * R[6] + a21 * R[7] + a22 * R[8];
+    // M = Sigma^-1 by cofactors
+    const float k00 = s11 * s22 - s12 * s12;
+    const float k01 = s02 * s12 - s01 * s22;
+    const float k02 = s01 * s12 - s02 * s11;
+    const float det = s00 * k00 + s01 * k01 + s02 * k02;
+    if (!(det > 0.f)) return;
+    const float id = 1.f / det;
+    const float m00 = k00 * id, m01 = k01 * id, m02 = k02 * id;
+    const float m11 = (s00 * s22 - s02 * s02) * id;
+    const float m12 = (s01 * s02 - s00 * s12) * id;
+    const float m22 = (s00 * s11 - s01 * s01) * id;
+    // residual
+    const float dx = mu.x - qx, dy = mu.y - qy, dz = mu.z - qz;
+    const float md0 = m00 * dx + m01 * dy + m02 * dz;
+    const float md1 = m01 * dx + m11 * dy + m12 * dz;
+    const float md2 = m02 * dx + m12 * dy + m22 * dz;
+    // B = M [q]x, [q]x = [[0,-qz,qy],[qz,0,-qx],[-qy,qx,0]]
+    const float b00 = m01 * qz - m02 * qy, b01 = m02 * qx - m00 * qz, b02 = m00 * qy - m01 * qx;
+    const float b10 = m11 * qz - m12 * qy, b11 = m12 * qx - m01 * qz, b12 = m01 * qy - m11 * qx;
+    const float b20 = m12 * qz - m22 * qy, b21 = m22 * qx - m02 * qz, b22 = m02 * qy - m12 * qx;
+    // H_ww = [q]x^T B: row i of [q]x^T is column i of [q]x
+    // column 0 of [q]x = (0, qz, -qy); column 1 = (-qz, 0, qx); column 2 = (qy, -qx, 0)
+    const float h00 = qz * b10 - qy * b20;
+    const float h01 = qz * b11 - qy * b21;
+    const float h02 = qz * b12 - qy * b22;
+    const float h11 = -qz * b01 + qx * b21;
+    const float h12 = -qz * b02 + qx * b22;
+    const float h22 = qy * b02 - qx * b12;
+    // H_wv = -B^T, H_vv = M
+    ACC_ADD(0, h00); ACC_ADD(1, h01); ACC_ADD(2, h02);
+    ACC_ADD(3, -b00); ACC_ADD(4, -b10); ACC_ADD(5, -b20);
+    ACC_ADD(6, h11); ACC_ADD(7, h12);
+    ACC_ADD(8, -b01); ACC_ADD(9, -b11); ACC_ADD(10, -b21);
+    ACC_ADD(11, h22);
+    ACC_ADD(12, -b02); ACC_ADD(13, -b12); ACC_ADD(14, -b22);
+    ACC_ADD(15, m00); ACC_ADD(16, m01); ACC_ADD(17, m02);
+    ACC_ADD(18, m11); ACC_ADD(19, m12);
+    ACC_ADD(20, m22);
+    // b = [ [q]x^T M d ; -M d ],  [q]x^T v = v x q
+    ACC_ADD(21, md1 * qz - md2 * qy);
+    ACC_ADD(22, md2 * qx - md0 * qz);
+    ACC_ADD(23, md0 * qy - md1 * qx);
+    ACC_ADD(24, -md0); ACC_ADD(25, -md1); ACC_ADD(26, -md2);
+    ACC_ADD(27, dx * md0 + dy * md1 + dz * md2);
+    ACC_ADD(28, 1.f);
+#undef ACC_ADD
+}
 
-    Acc<ACC> acc;
-    acc.zero();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float x = src[i], y = src[n + i], z = src[2 * n + i];
-        const float qx = R[0] * x + R[1] * y + R[2] * z + t[0];
-        const float qy = R[3] * x + R[4] * y + R[5] * z + t[1];
-        const float qz = R[6] * x + R[7] * y + R[8] * z + t[2];
-        const int32_t pos = nearest(map, qx, qy, qz);
-        if (pos < 0) continue;
-        const float4 mu = map.g.spts[pos];
-        const float4 ca = map.scov[2 * pos];
-        const float4 cb = map.scov[2 * pos + 1];
-        // source covariance rotated: A = R Cs, S = A R^T
-        const float c00 = scov[i], c01 = scov[n + i], c02 = scov[2 * n + i];
-        const float c11 = scov[3 * n + i], c12 = scov[4 * n + i], c22 = scov[5 * n + i];
-        const float a00 = R[0] * c00 + R[1] * c01 + R[2] * c02;
-        const float a01 = R[0] * c01 + R[1] * c11 + R[2] * c12;
-        const float a02 = R[0] * c02 + R[1] * c12 + R[2] * c22;
-        const float a10 = R[3] * c00 + R[4] * c01 + R[5] * c02;
-        const float a11 = R[3] * c01 + R[4] * c11 + R[5] * c12;
-        const float a12 = R[3] * c02 + R[4] * c12 + R[5] * c22;
-        const float a20 = R[6] * c00 + R[7] * c01 + R[8] * c02;
-        const float a21 = R[6] * c01 + R[7] * c11 + R[8] * c12;
-        const float a22 = R[6] * c02 + R[7] * c12 + R[8] * c22;
-        const float s00 = ca.x + a00 * R[0] + a01 * R[1] + a02 * R[2];
-        const float s01 = ca.y + a00 * R[3] + a01 * R[4] + a02 * R[5];
-        const float s02 = ca.z + a00 * R[6] + a01 * R[7] + a02 * R[8];
-        const float s11 = ca.w + a10 * R[3] + a11 * R[4] + a12 * R[5];
-        const float s12 = cb.x + a10 * R[6] + a11 * R[7] + a12 * R[8];
-        const float s22 = cb.y + a20 * R[6] + a21 * R[7] + a22 * R[8];
-        // M = Sigma^-1 by cofactors
-        const float k00 = s11 * s22 - s12 * s12;
-        const float k01 = s02 * s12 - s01 * s22;
-        const float k02 = s01 * s12 - s02 * s11;
-        const float det = s00 * k00 + s01 * k01 + s02 * k02;
-        if (!(det > 0.f)) continue;
-        const float id = 1.f / det;
-        const float m00 = k00 * id, m01 = k01 * id, m02 = k02 * id;
-        const float m11 = (s00 * s22 - s02 * s02) * id;
-        const float m12 = (s01 * s02 - s00 * s12) * id;
-        const float m22 = (s00 * s11 - s01 * s01) * id;
-        // residual
-        const float dx = mu.x - qx, dy = mu.y - qy, dz = mu.z - qz;
-        const float md0 = m00 * dx + m01 * dy + m02 * dz;
-        const float md1 = m01 * dx + m11 * dy + m12 * dz;
-        const float md2 = m02 * dx + m12 * dy + m22 * dz;
-        // B = M [q]x, [q]x = [[0,-qz,qy],[qz,0,-qx],[-qy,qx,0]]
-        const float b00 = m01 * qz - m02 * qy, b01 = m02 * qx - m00 * qz, b02 = m00 * qy - m01 * qx;
-        const float b10 = m11 * qz - m12 * qy, b11 = m12 * qx - m01 * qz, b12 = m01 * qy - m11 * qx;
-        const float b20 = m12 * qz - m22 * qy, b21 = m22 * qx - m02 * qz, b22 = m02 * qy - m12 * qx;
-        // H_ww = [q]x^T B: row i of [q]x^T is column i of [q]x
-        // column 0 of [q]x = (0, qz, -qy); column 1 = (-qz, 0, qx); column 2 = (qy, -qx, 0)
-        const float h00 = qz * b10 - qy * b20;
-        const float h01 = qz * b11 - qy * b21;
-        const float h02 = qz * b12 - qy * b22;
-        const float h11 = -qz * b01 + qx * b21;
-        const float h12 = -qz * b02 + qx * b22;
-        const float h22 = qy * b02 - qx * b12;
-        // H_wv = -B^T, H_vv = M
-        acc.add(0, h00); acc.add(1, h01); acc.add(2, h02);
-        acc.add(3, -b00); acc.add(4, -b10); acc.add(5, -b20);
-        acc.add(6, h11); acc.add(7, h12);
-        acc.add(8, -b01); acc.add(9, -b11); acc.add(10, -b21);
-        acc.add(11, h22);
-        acc.add(12, -b02); acc.add(13, -b12); acc.add(14, -b22);
-        acc.add(15, m00); acc.add(16, m01); acc.add(17, m02);
-        acc.add(18, m11); acc.add(19, m12);
-        acc.add(20, m22);
-        // b = [ [q]x^T M d ; -M d ],  [q]x^T v = v x q
-        acc.add(21, md1 * qz - md2 * qy);
-        acc.add(22, md2 * qx - md0 * qz);
-        acc.add(23, md0 * qy - md1 * qx);
-        acc.add(24, -md0); acc.add(25, -md1); acc.add(26, -md2);
-        acc.add(27, dx * md0 + dy * md1 + dz * md2);
-        acc.add(28, 1.f);
-    }
+// Workgroup reduction of the accumulators into 29 FP64 values at out[0..29).
+template <int ACC>
+__device__ __forceinline__ void block_reduce(Acc<ACC>& acc, double* __restrict__ out) {
     acc.wave_reduce();
     __shared__ double s_w[kBlock / 64][kNumAcc];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -260,8 +269,28 @@ __global__ __launch_bounds__(kBlock) void k_gn_linearize(const float* __restrict
             v = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) v += s_w[w][threadIdx.x];
         }
-        partials[(int64_t)blockIdx.x * kNumAcc + threadIdx.x] = v;
+        out[threadIdx.x] = v;
     }
+
+    __syncthreads();
+}
+
+template <int ACC>
+__global__ __launch_bounds__(kBlock) void k_gn_linearize(const float* __restrict__ src,
+                                                         const float* __restrict__ scov, int64_t n, MapView map,
+                                                         const RegState* __restrict__ st,
+                                                         double* __restrict__ partials) {
+    if (st->done) return;
+    float R[9], t[3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
+    Acc<ACC> acc;
+    acc.zero();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        linearize_point<ACC>(src, scov, n, i, map, R, t, acc);
+    block_reduce<ACC>(acc, partials + (int64_t)blockIdx.x * kNumAcc);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,42 +331,12 @@ __device__ __forceinline__ void exp_se3(const double xi[6], double T[16]) {
     T[15] = 1.0;
 }
 
-constexpr int kSolveThreads = 256;
-constexpr int kSolveParts = 8;
+}  // namespace
 
-__global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __restrict__ partials, int nblocks,
-                                                            RegState* __restrict__ st) {
-    if (st->done) return;
-    __shared__ double s_part[kNumAcc][kSolveParts];
-    const int acc = st->acc;
-    const int t = threadIdx.x;
-    if (t < kNumAcc * kSolveParts) {
-        const int j = t / kSolveParts, p = t % kSolveParts;
-        if (acc == GICP_ACC_FP32) {
-            float f = 0.f;
-            for (int b = p; b < nblocks; b += kSolveParts) f += (float)partials[(int64_t)b * kNumAcc + j];
-            s_part[j][p] = (double)f;
-        } else {
-            double v = 0.0;
-            for (int b = p; b < nblocks; b += kSolveParts) v += partials[(int64_t)b * kNumAcc + j];
-            s_part[j][p] = v;
-        }
-    }
-    __syncthreads();
-    if (t != 0) return;
-    double v[kNumAcc];
-    for (int j = 0; j < kNumAcc; ++j) {
-        if (acc == GICP_ACC_FP32) {
-            float f = 0.f;
-            for (int p = 0; p < kSolveParts; ++p) f += (float)s_part[j][p];
-            v[j] = (double)f;
-        } else {
-            double s = 0.0;
-            for (int p = 0; p < kSolveParts; ++p) s += s_part[j][p];
-            v[j] = s;
-        }
-    }
-    double H[36];
+// Thread-0 part of the solve: v holds the 29 reduced sums; H and L live in
+// LDS (workspace of 72 doubles) so that the single-thread FP64 solve does not
+// raise the register footprint of the kernels that embed it.
+__device__ __noinline__ void solve_update(const double* v, RegState* st, double* H, double* L) {
     int q = 0;
     for (int i = 0; i < 6; ++i)
         for (int j = i; j < 6; ++j) {
@@ -359,7 +358,6 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __rest
     double dmax = 0.0;
     for (int i = 0; i < 6; ++i) dmax = fmax(dmax, H[7 * i]);
     const double floor_ = 1e-12 * dmax;
-    double L[36];
     for (int i = 0; i < 36; ++i) L[i] = 0.0;
     for (int j = 0; j < 6; ++j) {
         double s = H[7 * j];
@@ -388,7 +386,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __rest
         xi[i] = r / L[7 * i];
     }
     for (int i = 0; i < 6; ++i) xi[i] = -xi[i];
-    double E[16], T[16];
+    // T <- Exp(xi) T, with Exp in L[0..16) and the product in H[0..16) (both free now)
+    double* E = L;
+    double* T = H;
     exp_se3(xi, E);
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
@@ -411,6 +411,174 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __rest
     }
 }
 
+namespace {
+
+constexpr int kSolveThreads = 256;
+constexpr int kSolveParts = 8;
+
+}  // namespace
+
+// Reduction of `nparts` FP64 partials (29 values each) in a fixed order, then
+// (thread 0) the 6x6 Cholesky solve, the SE(3) update and the convergence
+// test.  Called by all kSolveThreads threads of one workgroup.
+__device__ void solve_state(const double* __restrict__ partials, int nparts, RegState* __restrict__ st) {
+    __shared__ double s_part[kNumAcc][kSolveParts];
+    __shared__ double s_v[kNumAcc];
+    __shared__ double s_HL[72];
+    const int acc = st->acc;
+    const int t = threadIdx.x;
+    if (t < kNumAcc * kSolveParts) {
+        const int j = t / kSolveParts, p = t % kSolveParts;
+        if (acc == GICP_ACC_FP32) {
+            float f = 0.f;
+            for (int b = p; b < nparts; b += kSolveParts) f += (float)partials[(int64_t)b * kNumAcc + j];
+            s_part[j][p] = (double)f;
+        } else {
+            double v = 0.0;
+            for (int b = p; b < nparts; b += kSolveParts) v += partials[(int64_t)b * kNumAcc + j];
+            s_part[j][p] = v;
+        }
+    }
+    __syncthreads();
+    if (t < kNumAcc) {
+        if (acc == GICP_ACC_FP32) {
+            float f = 0.f;
+            for (int p = 0; p < kSolveParts; ++p) f += (float)s_part[t][p];
+            s_v[t] = (double)f;
+        } else {
+            double s = 0.0;
+            for (int p = 0; p < kSolveParts; ++p) s += s_part[t][p];
+            s_v[t] = s;
+        }
+    }
+    __syncthreads();
+    if (t == 0) solve_update(s_v, st, s_HL, s_HL + 36);
+    __syncthreads();
+}
+
+namespace {
+
+__global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __restrict__ partials, int nblocks,
+                                                            RegState* __restrict__ st) {
+    if (st->done) return;
+    solve_state(partials, nblocks, st);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work queue over (problem, chunk) items.  Workers pop items in
+// ticket order; an item is one chunk of kChunk source points of one problem at
+// the problem's current pose.  The worker that completes the last chunk of a
+// problem's iteration reduces that iteration's partials (fixed slots, fixed
+// order: results do not depend on scheduling), solves, updates the pose and
+// either pushes the problem's chunks for the next iteration or retires the
+// problem.  Workers leave when every problem is retired.  Every wait is bounded
+// (kSpinLimit sleeps) and sets the queue's error word when exhausted.
+// ---------------------------------------------------------------------------
+constexpr long long kSpinLimit = 1ll << 24;
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int ACC>
+__global__ __launch_bounds__(kBlock) void k_gn_queue(const ProbDev* __restrict__ probs, QueueDev* __restrict__ q,
+                                                     uint32_t* __restrict__ items, uint32_t* __restrict__ arrive,
+                                                     double* __restrict__ partials) {
+    __shared__ uint32_t s_item;
+    __shared__ int s_last;
+    __shared__ uint32_t s_base;
+    const uint32_t cap = q->cap;
+    while (true) {
+        if (threadIdx.x == 0) {
+            const uint32_t tk = atomicAdd(&q->head, 1u);
+            uint32_t it = 0;
+            long long spins = 0;
+            while (true) {
+                if (tk < cap) it = load_agent(&items[tk]);
+                if (it != 0u) break;
+                if (load_agent(&q->remaining) == 0u || tk >= cap) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    atomicOr(&q->error, 1u);
+                    break;
+                }
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item == 0u) return;
+        __threadfence();  // acquire: the problem's state as of the push of this item
+        const uint32_t p = (item - 1u) >> kChunkBits, c = (item - 1u) & ((1u << kChunkBits) - 1u);
+        const ProbDev P = probs[p];
+        RegState* st = P.st;
+        float R[9], t[3];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
+        Acc<ACC> acc;
+        acc.zero();
+        const int64_t i = (int64_t)c * kChunk + threadIdx.x;
+        if (i < P.n) linearize_point<ACC, true>(P.src, P.scov, P.n, i, P.map, R, t, acc);
+        block_reduce<ACC>(acc, partials + ((int64_t)P.part0 + c) * kNumAcc);
+        if (threadIdx.x == 0) {
+            __threadfence();  // release this chunk's partial
+            s_last = (atomicAdd(&arrive[p], 1u) == (uint32_t)P.nchunks - 1u) ? 1 : 0;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();  // acquire the other chunks' partials
+            solve_state(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
+            if (threadIdx.x == 0) {
+                atomicExch(&arrive[p], 0u);
+                __threadfence();  // release the new state before it is announced
+                if (st->done) {
+                    s_base = 0xFFFFFFFFu;
+                    atomicSub(&q->remaining, 1u);
+                } else {
+                    s_base = atomicAdd(&q->tail, (uint32_t)P.nchunks);
+                }
+            }
+            __syncthreads();
+            const uint32_t base = s_base;
+            if (base != 0xFFFFFFFFu) {
+                __threadfence();
+                for (int j = threadIdx.x; j < P.nchunks; j += kBlock)
+                    if (base + (uint32_t)j < cap)
+                        __hip_atomic_store(&items[base + j], ((p << kChunkBits) | (uint32_t)j) + 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Queue set-up: zero the item ring and the arrival counters, post every
+// problem's first-iteration chunks (item slots = partial slots), and reset the
+// queue counters.
+__global__ void k_queue_init(const ProbDev* __restrict__ probs, int nprob, QueueDev* __restrict__ q,
+                             uint32_t* __restrict__ items, uint32_t cap, uint32_t first, uint32_t* __restrict__ arrive) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t j = i; j < cap; j += gridDim.x * blockDim.x) items[j] = 0u;
+    for (uint32_t j = i; j < (uint32_t)nprob; j += gridDim.x * blockDim.x) arrive[j] = 0u;
+    if (i == 0) {
+        q->head = 0u;
+        q->tail = first;
+        q->remaining = (uint32_t)nprob;
+        q->error = 0u;
+        q->cap = cap;
+    }
+}
+
+__global__ void k_queue_post(const ProbDev* __restrict__ probs, int nprob, uint32_t* __restrict__ items) {
+    const int p = blockIdx.x;
+    if (p >= nprob) return;
+    const ProbDev P = probs[p];
+    for (int c = threadIdx.x; c < P.nchunks; c += blockDim.x)
+        items[P.part0 + c] = (((uint32_t)p << kChunkBits) | (uint32_t)c) + 1u;
+}
+
 }  // namespace
 
 int gn_blocks(int64_t n) {
@@ -418,7 +586,7 @@ int gn_blocks(int64_t n) {
     return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
-hipError_t launch_gn_iteration(const float* src, const float* scov, int64_t n, const MapView& map, RegState* st,
+hipError_t launch_gn_linearize(const float* src, const float* scov, int64_t n, const MapView& map, RegState* st,
                                double* partials, int nblocks, int acc, hipStream_t s) {
     switch (acc) {
         case GICP_ACC_FP32:
@@ -433,7 +601,42 @@ hipError_t launch_gn_iteration(const float* src, const float* scov, int64_t n, c
             hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_TWOSUM>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
                                (const RegState*)st, partials);
     }
-    hipLaunchKernelGGL(k_gn_solve, dim3(1), dim3(kSolveThreads), 0, s, (const double*)partials, nblocks, st);
+    return hipGetLastError();
+}
+
+int gn_queue_workers(int acc) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    hipError_t e;
+    switch (acc) {
+        case GICP_ACC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<GICP_ACC_FP32>, kBlock, 0); break;
+        case GICP_ACC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<GICP_ACC_FP64>, kBlock, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<GICP_ACC_TWOSUM>, kBlock, 0);
+    }
+    if (e != hipSuccess || per < 1) per = 1;
+    return cus * per;
+}
+
+hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_t* items, uint32_t cap,
+                           uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_queue_init, dim3(64), dim3(256), 0, s, probs, nprob, q, items, cap, first, arrive);
+    hipLaunchKernelGGL(k_queue_post, dim3(nprob), dim3(256), 0, s, probs, nprob, items);
+    switch (acc) {
+        case GICP_ACC_FP32:
+            hipLaunchKernelGGL(k_gn_queue<GICP_ACC_FP32>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
+            break;
+        case GICP_ACC_FP64:
+            hipLaunchKernelGGL(k_gn_queue<GICP_ACC_FP64>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
+            break;
+        default:
+            hipLaunchKernelGGL(k_gn_queue<GICP_ACC_TWOSUM>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_gn_solve, dim3(1), dim3(kSolveThreads), 0, s, partials, nblocks, st);
     return hipGetLastError();
 }
 

@@ -1,13 +1,15 @@
 // Uniform-grid spatial hash: cell keys, a stable LSD radix sort of 30-bit keys
-// (three 10-bit digits), and the open-addressing cell table.
+// (four 8-bit digit passes), and the open-addressing cell table.
 //
 // Radix sort design for wave64: each pass is (1) a per-tile digit histogram,
-// (2) an exclusive scan over the digit-major [1024][tiles] count matrix, and
+// (2) an exclusive scan over the digit-major [256][tiles] count matrix, and
 // (3) a stable scatter.  Within a tile, elements are processed in rounds of
 // 256 (one per lane, in order); lanes holding the same digit are found with
-// ten wavefront ballots, their rank is the popcount of the lower lanes of the
-// match mask, and per-wave digit totals in LDS order the four waves.  Equal
-// digits therefore keep input order, which makes the sort stable.
+// eight wavefront ballots, their rank is the popcount of the lower lanes of
+// the match mask, and per-wave digit totals in LDS order the four waves.
+// Equal digits therefore keep input order, which makes the sort stable.
+// Tiles of 1024 keys keep a 60k-point frame at ~60 workgroups and its count
+// matrix inside one scan workgroup.
 #include <algorithm>
 
 #include "common.hpp"
@@ -17,12 +19,13 @@ namespace gicp {
 
 namespace {
 
-constexpr int kDigitBits = 10;
+constexpr int kDigitBits = 8;
+constexpr int kPasses = 4;                     // 30-bit keys
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kIpt = 16;                       // rounds (elements per thread) per tile
-constexpr int kTile = kSortThreads * kIpt;     // 4096
+constexpr int kIpt = 4;                        // rounds (elements per thread) per tile
+constexpr int kTile = kSortThreads * kIpt;     // 1024
 constexpr int kScanThreads = 1024;
 constexpr int kScanIpt = 16;
 constexpr int kScanChunk = kScanThreads * kScanIpt;
@@ -251,7 +254,7 @@ hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, u
     uint32_t* vin = vals_a;
     uint32_t* kout = keys_b;
     uint32_t* vout = vals_b;
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < kPasses; ++pass) {
         const int shift = pass * kDigitBits;
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n, shift, ntiles, counts);
         if (nchunks > 1) {
@@ -267,7 +270,8 @@ hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, u
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
-    // three passes: the result sits in (keys_b, vals_b)
+    // an even number of passes leaves the result in (keys_a, vals_a)
+    static_assert(kPasses % 2 == 0, "pass parity");
     return hipGetLastError();
 }
 

@@ -56,17 +56,34 @@ __device__ __forceinline__ void scan_cell(const GridView& g, uint32_t key, float
     }
 }
 
-// Exact k-NN of q: returns false only if even the full scan was needed and
-// used (never inexact: the full scan is exact by construction).
+// Current pruning bound: the k-th key once the list is full (else +inf),
+// capped by the gate.
 template <int K>
-__device__ __forceinline__ void knn_search(const GridView& g, float qx, float qy, float qz, int k, float gate2, float r_gate,
-                           TopK<K>& top) {
+__device__ __forceinline__ float prune_bound(const TopK<K>& top, float gate2) {
+    const uint64_t w = top.v[K - 1];
+    const float kth = (w == ~0ull) ? FLT_MAX : __uint_as_float((uint32_t)(w >> 32));
+    return fminf(kth, gate2);
+}
+
+// Exact k-NN of q.  The 27-cell block is visited nearest cell first, and a
+// cell is skipped when its distance lower bound already exceeds the current
+// k-th key (or the gate).  Exactness is then proven from the block clearance;
+// otherwise the next shell of cells is visited (with the same pruning), and
+// after kMaxShell shells the whole cloud is scanned.
+template <int K>
+__device__ __forceinline__ void knn_search(const GridView& g, float qx, float qy, float qz, int k, float gate2,
+                                           float r_gate, TopK<K>& top) {
     top.init(k);
+    if (!finite3(qx, qy, qz)) return;   // no neighbour has a finite distance
     const Cell c = cell_of(qx, qy, qz, g.inv_h);
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx)
-                scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+    const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
+    for (int j = 0; j < 27; ++j) {
+        int dx, dy, dz;
+        block_offset(j, dx, dy, dz);
+        const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, g.h, slack);
+        if (cell_pruned(lb, prune_bound(top, gate2))) continue;
+        scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+    }
     for (int R = 1;; ++R) {
         const float clr = block_clearance(qx, qy, qz, c, R, g.h);
         if (clr > 0.f) {
@@ -83,6 +100,8 @@ __device__ __forceinline__ void knn_search(const GridView& g, float qx, float qy
             for (int dy = -S; dy <= S; ++dy)
                 for (int dx = -S; dx <= S; ++dx) {
                     if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
+                    const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, g.h, slack);
+                    if (cell_pruned(lb, prune_bound(top, gate2))) continue;
                     scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
                 }
     }

@@ -9,8 +9,8 @@
 namespace gicp {
 
 // Scratch the radix sort needs for n keys (bytes), and the launcher.  Sorts
-// 30-bit keys with their values stably: (keys_a, vals_a) -> (keys_b, vals_b);
-// keys_a/vals_a are clobbered.
+// 30-bit keys with their values stably, in place in (keys_a, vals_a), using
+// (keys_b, vals_b) as the ping-pong buffers.
 size_t radix_scratch_bytes(int64_t n);
 hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                          int64_t n, void* scratch, hipStream_t s);
@@ -69,8 +69,36 @@ struct MapView {
     float r_max, r_max2;
 };
 
+// One registration problem of the work-queue kernel.
+struct ProbDev {
+    const float* src;     // SoA [3][n]
+    const float* scov;    // SoA [6][n]
+    int64_t n;
+    int32_t nchunks;      // ceil(n / kChunk)
+    int32_t part0;        // first partial / item slot of the problem
+    MapView map;
+    RegState* st;
+};
+
+struct QueueDev {
+    uint32_t head;        // next ticket
+    uint32_t tail;        // item slots reserved so far
+    uint32_t remaining;   // problems not yet retired
+    uint32_t error;       // set when a bounded wait ran out
+    uint32_t cap;         // item ring capacity
+    uint32_t pad[3];
+};
+
+constexpr int kChunk = 256;          // source points per work item
+constexpr int kChunkBits = 20;       // item = ((problem << 20) | chunk) + 1
+constexpr int kMaxProblems = 4096;
+
 int gn_blocks(int64_t n);
-hipError_t launch_gn_iteration(const float* src, const float* scov, int64_t n, const MapView& map,
-                               RegState* st, double* partials, int nblocks, int acc, hipStream_t s);
+int gn_queue_workers(int acc);
+hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_t* items, uint32_t cap,
+                           uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, hipStream_t s);
+hipError_t launch_gn_linearize(const float* src, const float* scov, int64_t n, const MapView& map, RegState* st,
+                               double* partials, int nblocks, int acc, hipStream_t s);
+hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
 
 }  // namespace gicp

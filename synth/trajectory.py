@@ -43,24 +43,23 @@ def smooth_trajectory(seed: int, n_frames: int = 100, extent=(4.0, 4.0, 3.0),
         T[:3, 3] = sp(s)
         return T
 
-    # re-time: advance s in small increments, emit a frame whenever the next
-    # increment would break the per-frame bound (with a 10% margin)
-    dense = np.linspace(0.0, n_ctrl, 20001)
-    poses = [pose(dense[0])]
+    # re-time: walk along the periodic spline in small increments and emit a
+    # frame whenever the next increment would break the per-frame bound (with a
+    # 10% margin); the walk wraps around the loop as often as needed
+    ds = n_ctrl / 20000.0
+    poses = [pose(0.0)]
     last = poses[0]
     prev_T = last
-    for s in dense[1:]:
-        T = pose(s)
+    s_cur = 0.0
+    while len(poses) < n_frames:
+        s_cur += ds
+        T = pose(s_cur % n_ctrl)
         dt = np.linalg.norm(T[:3, 3] - last[:3, 3])
         dr = np.degrees(Rotation.from_matrix(last[:3, :3].T @ T[:3, :3]).magnitude())
         if dt > 0.9 * max_step_m or dr > 0.9 * max_step_deg:
             poses.append(prev_T)
             last = prev_T
-            if len(poses) == n_frames:
-                break
         prev_T = T
-    while len(poses) < n_frames:
-        poses.append(prev_T)
     return np.stack(poses)
 
 

@@ -1,0 +1,136 @@
+"""The persistent work-queue path: identical to per-iteration launches and to
+single registrations (bitwise), per-problem statuses, and oracle parity of a
+batch of uneven problems."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import covariance as oc
+from oracle import gicp as og
+from oracle import se3
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2403_12550_amd as g
+    g.lib()
+    return g
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    import torch
+    torch.cuda.set_device(0)
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def _c1(g, ctx, n=5000, seed=0):
+    pr = synth.c1_problem(n=n, room_seed=seed, src_seed=seed + 1, tgt_seed=seed + 2, tf_seed=seed + 3)
+    src, tgt = g.to_soa(pr.src), g.to_soa(pr.tgt)
+    tcov = ctx.covariances(tgt, 20, reg_mode=1)
+    gm = ctx.map_build(tgt, tcov, cell=0.1)
+    return pr, src, gm
+
+
+@pytest.mark.parametrize("acc", [0, 1, 2])
+def test_queue_equals_multi_launch(g, ctx, acc):
+    _say("queue_vs_multi", acc)
+    pr, src, gm = _c1(g, ctx)
+    a = ctx.register(src, gm, pr.init, g.params(max_it=30, precision=acc))
+    b = ctx.register(src, gm, pr.init, g.params(max_it=30, precision=acc, flags=g.FLAG_MULTI_LAUNCH))
+    assert a.status == b.status == 0 and a.iters == b.iters == 30
+    # the two paths evaluate the same expressions with the same chunking and
+    # summation order; they are expected to agree bitwise, and must agree to
+    # rounding level
+    _say("  bitwise:", bool((a.pose == b.pose).all() and (a.H == b.H).all()))
+    assert np.allclose(a.pose, b.pose, rtol=0, atol=1e-12)
+    assert np.allclose(a.H, b.H, rtol=1e-12, atol=0)
+
+
+def test_queue_early_exit_matches(g, ctx):
+    _say("queue_early_exit")
+    pr, src, gm = _c1(g, ctx)
+    prm = dict(max_it=30, conv_rot=1e-6, conv_trans=1e-6)
+    a = ctx.register(src, gm, pr.init, g.params(**prm))
+    b = ctx.register(src, gm, pr.init, g.params(flags=g.FLAG_MULTI_LAUNCH, **prm))
+    assert a.converged and b.converged and a.iters == b.iters < 30
+    assert np.allclose(a.pose, b.pose, rtol=0, atol=1e-12)
+
+
+def _batch_problems(g, ctx, sizes, seed0=5000):
+    import torch
+    out = []
+    for i, (ns, m) in enumerate(sizes):
+        rng = np.random.default_rng(seed0 + i)
+        room = synth.make_room(seed0 + i)
+        tp, tn = synth.sample_surface(room, m, seed0 + i + 1, 0.001)
+        sp, _ = synth.sample_surface(room, ns, seed0 + i + 2, 0.002)
+        T = synth.random_offset(rng, 3.0, 0.05)
+        src = (sp - T[:3, 3]) @ T[:3, :3]
+        cov = synth.disc_covariances(tn, seed0 + i + 3)
+        means = g.to_soa(tp.astype(np.float32))
+        gm = ctx.map_build(means, g.to_soa(cov.astype(np.float32)), cell=0.0, reg_mode=1)
+        out.append(dict(src_np=src.astype(np.float32), tgt_np=tp.astype(np.float32), cov_np=cov.astype(np.float32),
+                        src=g.to_soa(src.astype(np.float32)), map=gm, T=T))
+        torch.cuda.synchronize()
+    return out
+
+
+def test_batch_equals_single(g, ctx):
+    _say("batch_vs_single")
+    sizes = [(2000, 30000), (7000, 60000), (15000, 20000), (300, 50000), (40000, 100000)]
+    probs = _batch_problems(g, ctx, sizes)
+    prm = g.params(max_it=20, conv_rot=1e-6, conv_trans=1e-6, cell_src=0.0)
+    batch = ctx.register_batch([(p["src"], None, p["map"], np.eye(4)) for p in probs], prm)
+    for p, rb in zip(probs, batch):
+        rs = ctx.register(p["src"], p["map"], np.eye(4), prm)
+        assert rb.status == rs.status == 0
+        assert rb.iters == rs.iters
+        assert (rb.pose == rs.pose).all() and (rb.H == rs.H).all()
+    for p in probs:
+        p["map"].close()
+
+
+def test_batch_oracle_parity(g, ctx):
+    _say("batch_oracle")
+    sizes = [(3000, 40000), (9000, 80000)]
+    probs = _batch_problems(g, ctx, sizes, seed0=6000)
+    prm = g.params(max_it=20, conv_rot=1e-6, conv_trans=1e-6)
+    batch = ctx.register_batch([(p["src"], None, p["map"], np.eye(4)) for p in probs], prm)
+    for p, rb in zip(probs, batch):
+        cs = oc.covariances(p["src_np"], 20)
+        ct = oc.regularise6(p["cov_np"], oc.REG_PLANE, 1e-3)
+        o = og.register(p["src_np"], cs, p["tgt_np"], ct, np.eye(4), r_max=0.1, max_it=20,
+                        conv_rot=1e-6, conv_trans=1e-6)
+        dr, dt = se3.pose_error(rb.pose, o.pose)
+        _say(f"  rot {dr:.2e} trans {dt:.2e} it {rb.iters}/{o.iters}")
+        assert dr < 1e-5 and dt < 1e-5
+        p["map"].close()
+
+
+def test_batch_statuses(g, ctx):
+    _say("batch_statuses")
+    pr, src, gm = _c1(g, ctx, n=2000)
+    far = np.eye(4)
+    far[:3, 3] = [30, 0, 0]
+    res = ctx.register_batch([(src, None, gm, np.eye(4)), (src, None, gm, far), (src, None, gm, np.eye(4))],
+                             g.params(max_it=10))
+    assert [r.status for r in res] == [0, 3, 0]
+    assert res[1].iters == 1 and np.allclose(res[1].pose, far)
+    assert (res[0].pose == res[2].pose).all()
+
+
+def test_batch_arg_errors(g, ctx):
+    pr, src, gm = _c1(g, ctx, n=500)
+    with pytest.raises(g.GicpError):
+        ctx.register_batch([], g.params())
+    with pytest.raises(g.GicpError):
+        ctx.register_batch([(src, None, gm, np.eye(4))], g.params(r_max=-1.0))
