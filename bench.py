@@ -92,17 +92,42 @@ def run_oracle(seq, n_frames, r_max, max_it, conv, closed_loop=False):
     return est, secs, setup
 
 
+def time_frames(ctx, gmap, frames, seq, prm, order, batch, prof=False):
+    """Registers the frames listed in `order` in groups of `batch`; returns
+    (seconds, poses by frame, iterations, statuses)."""
+    import torch
+    poses, iters, statuses = {}, [], []
+    if prof:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s0 in range(0, len(order), batch):
+        idx = order[s0:s0 + batch]
+        if batch == 1:
+            i = idx[0]
+            rs = [ctx.register(frames[i], gmap, cv_init(seq, seq.poses, i), prm)]
+        else:
+            rs = ctx.register_batch([(frames[i], None, gmap, cv_init(seq, seq.poses, i)) for i in idx], prm)
+        for i, r in zip(idx, rs):
+            poses[i] = r.pose
+            iters.append(r.iters)
+            statuses.append(r.status)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, poses, iters, statuses
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=95)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100, help="timed frames")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed frames before the timed ones")
+    ap.add_argument("--batch", type=int, default=20, help="frames per gicp_register_batch call")
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--map-size", type=int, default=1_000_000)
+    ap.add_argument("--map-cell", type=float, default=0.03)
     ap.add_argument("--cpu-frames", type=int, default=4, help="frames the CPU oracle baseline registers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--closed-loop", action="store_true",
-                    help="initialise each frame from the previous estimates instead of the ground-truth poses")
+    ap.add_argument("--c4", action="store_true", help="also time the 64-problem batch workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -133,53 +158,36 @@ def main():
 
     # map: built once (static map), timed on its own
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    map_cell = ctx.estimate_cell(means, 8)
     ev0.record()
-    gmap = ctx.map_build(means, covs, cell=map_cell, reg_mode=g.REG_PLANE, eps=1e-3)
+    gmap = ctx.map_build(means, covs, cell=args.map_cell, reg_mode=g.REG_PLANE, eps=1e-3)
     ev1.record()
     torch.cuda.synchronize()
     map_ms = ev0.elapsed_time(ev1)
     src_cell = ctx.estimate_cell(frames[0], 20)
-    log(f"map built in {map_ms:.2f} ms (cell {map_cell * 100:.2f} cm); source cell {src_cell * 100:.2f} cm")
+    log(f"map built in {map_ms:.2f} ms (cell {gmap.cell * 100:.2f} cm); source cell {src_cell * 100:.2f} cm")
 
     r_max, max_it, conv = 0.1, 20, 1e-6
     prm = g.params(k=20, eps=1e-3, r_max=r_max, max_it=max_it, conv_rot=conv, conv_trans=conv,
                    reg_mode=g.REG_PLANE, cell_src=src_cell)
     nf = args.frames
-    est = {}
-    iters = []
-    statuses = []
+    warm = [i % nf for i in range(args.warmup)]
+    order = [(args.warmup + i) % nf for i in range(args.steps)]
 
-    def step(s):
-        i = s % nf
-        if i == 0:
-            est.clear()
-        init = cv_init(seq, est if args.closed_loop else seq.poses, i)
-        r = ctx.register(frames[i], gmap, init, prm)
-        est[i] = r.pose
-        return r
-
-    for s in range(args.warmup):
-        step(s)
-    first_poses = {i: p.copy() for i, p in est.items()}
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t1 = time.perf_counter()
-    for s in range(args.warmup, args.warmup + args.steps):
-        r = step(s)
-        iters.append(r.iters)
-        statuses.append(r.status)
-        if (s % nf) < args.cpu_frames:
-            first_poses[s % nf] = r.pose.copy()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
+    # plain per-frame form (one gicp_register call per frame)
+    time_frames(ctx, gmap, frames, seq, prm, warm, 1)
+    t_plain, _, _, _ = time_frames(ctx, gmap, frames, seq, prm, order, 1)
+    # batched form (the headline): `batch` frames per call, kernel timing on
+    time_frames(ctx, gmap, frames, seq, prm, warm, args.batch)
+    elapsed, poses, iters, statuses = time_frames(ctx, gmap, frames, seq, prm, order, args.batch, prof=True)
     prof = {gid: ctx.profile_read(gid) for gid in range(4)}
+    ctx.profile(False)
     fps = args.steps / elapsed
-    log(f"timed {args.steps} frames in {elapsed * 1e3:.1f} ms: {fps:.1f} frames/s, "
-        f"mean iterations {np.mean(iters):.2f}, statuses {sorted(set(statuses))}")
+    fps_plain = args.steps / t_plain
+    log(f"timed {args.steps} frames: batched ({args.batch}/call) {fps:.1f} frames/s, per-frame {fps_plain:.1f} "
+        f"frames/s; mean iterations {np.mean(iters):.2f}, statuses {sorted(set(statuses))}")
 
     # ground-truth error (information only: the synthetic frames are noisy resamples)
-    gt_err = np.array([pose_delta(p, seq.poses[i]) for i, p in est.items()])
+    gt_err = np.array([pose_delta(p, seq.poses[i]) for i, p in poses.items()])
 
     kernels = {}
     for gid, (n, ms, units) in prof.items():
@@ -195,20 +203,22 @@ def main():
                 "bytes_per_unit": BYTES_PER_UNIT[dom], "units_per_launch": units / n,
                 "avg_launch_us": 1e3 * ms / n}
 
+    c4 = run_c4(ctx, g) if args.c4 else None
+
     cpu = None
     err_vs_oracle = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         nc = min(args.cpu_frames, nf)
-        opos, secs, setup = run_oracle(seq, nc, r_max, max_it, conv, args.closed_loop)
-        # the GPU poses of frames 0..nc-1 from its own recursion
-        gpu_first = [first_poses.get(i, est.get(i)) for i in range(nc)]
-        errs = np.array([pose_delta(gp, op) for gp, op in zip(gpu_first, opos)])
+        opos, secs, setup = run_oracle(seq, nc, r_max, max_it, conv)
+        # the GPU poses of the same frames, from the same initial poses
+        _, gp, _, _ = time_frames(ctx, gmap, frames, seq, prm, list(range(nc)), args.batch)
+        errs = np.array([pose_delta(gp[i], op) for i, op in enumerate(opos)])
         err_vs_oracle = {"frames": nc, "max_rad": float(errs[:, 0].max()), "max_m": float(errs[:, 1].max())}
         cores = len(os.sched_getaffinity(0))
         cpu = {"value": round(nc / sum(secs), 4), "unit": "frames/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {nc} frames of the same trajectory (own constant-velocity recursion), "
-                         f"FP64 numpy/scipy, cKDTree workers=-1; per-frame time excludes the one-off "
-                         f"map preparation ({setup:.1f} s: eigh of 1M covariances + kd-tree)"}
+               "sample": f"first {nc} frames of the same workload and initial poses, FP64 numpy/scipy, "
+                         f"cKDTree workers=-1; per-frame time excludes the one-off map preparation "
+                         f"({setup:.1f} s: eigh of 1M covariances + kd-tree)"}
         log(f"cpu oracle: {cpu['value']} frames/s over {nc} frames; GPU vs oracle max "
             f"{err_vs_oracle['max_rad']:.2e} rad {err_vs_oracle['max_m']:.2e} m")
 
@@ -229,9 +239,12 @@ def main():
                                f"(mean {npts.mean():.0f} pts) vs a {args.map_size}-Gaussian map, "
                                f"{nf}-frame trajectory, k=20, plane eps=1e-3, r_max=0.1 m, <=20 GN it",
                    "frames": nf, "map_gaussians": args.map_size, "mean_points": float(npts.mean()),
-                   "form": "plain per-frame (one gicp_register call per frame)",
-                   "init": ("constant velocity from the previous two estimates" if args.closed_loop else
-                            "constant-velocity prediction from the previous two ground-truth poses")},
+                   "form": f"batched: {args.batch} frames per gicp_register_batch call; a step is one frame",
+                   "init": "constant-velocity prediction from the previous two ground-truth poses"},
+        "per_frame_form": {"value": round(fps_plain, 3), "unit": "frames/s",
+                           "ms_per_frame": round(1e3 * t_plain / args.steps, 4),
+                           "form": "one gicp_register call per frame"},
+        "batched_over_per_frame": round(fps / fps_plain, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pose_err_vs_oracle": err_vs_oracle,
@@ -239,10 +252,55 @@ def main():
         "mean_gn_iterations": float(np.mean(iters)),
         "map_build_ms": round(map_ms, 3),
         "kernels": kernels,
+        "c4_batch": c4,
     }
     print(json.dumps(out), flush=True)
     gmap.close()
     ctx.close()
+
+
+def run_c4(ctx, g, n_prob=64):
+    """The batched-registration workload: 64 problems (sources 2k-200k points,
+    targets 0.1M-1M Gaussians), one gicp_register_batch call."""
+    import torch
+
+    import synth
+    t0 = time.perf_counter()
+    probs = synth.c4_batch(n_prob=n_prob)
+    items, maps = [], []
+    for p in probs:
+        gm = ctx.map_build(g.to_soa(p.tgt), g.to_soa(p.tgt_cov_raw), cell=0.0, reg_mode=g.REG_PLANE)
+        maps.append(gm)
+        items.append((g.to_soa(p.src), None, gm, p.init))
+    torch.cuda.synchronize()
+    log(f"c4: {n_prob} problems generated and maps built in {time.perf_counter() - t0:.1f} s")
+    prm = g.params(k=20, eps=1e-3, r_max=0.1, max_it=30, conv_rot=1e-6, conv_trans=1e-6, reg_mode=g.REG_PLANE)
+    out = {}
+    for name, flags in (("batched", 0), ("queue", g.FLAG_QUEUE), ("per_problem", g.FLAG_MULTI_LAUNCH)):
+        p2 = g.params(k=20, eps=1e-3, r_max=0.1, max_it=30, conv_rot=1e-6, conv_trans=1e-6, reg_mode=g.REG_PLANE,
+                      flags=flags)
+        ctx.register_batch(items, p2)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t = time.perf_counter()
+        res = ctx.register_batch(items, p2)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        n, ms, u = ctx.profile_read(0)
+        ctx.profile(False)
+        terr = max(float(np.linalg.norm(r.pose[:3, 3] - p.T_gt[:3, 3])) for r, p in zip(res, probs))
+        out[name] = {"problems_per_s": round(n_prob / dt, 2), "ms": round(1e3 * dt, 3),
+                     "mean_iterations": float(np.mean([r.iters for r in res])),
+                     "statuses": sorted(set(int(r.status) for r in res)),
+                     "linearize_GBps": round(72.0 * u / (ms * 1e-3) / 1e9, 2) if ms > 0 else None,
+                     "max_trans_err_vs_truth_m": terr}
+        log(f"c4 {name}: {out[name]}")
+    for gm in maps:
+        gm.close()
+    out["source_points"] = int(sum(p.src.shape[0] for p in probs))
+    out["target_gaussians"] = int(sum(p.tgt.shape[0] for p in probs))
+    del prm
+    return out
 
 
 if __name__ == "__main__":

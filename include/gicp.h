@@ -91,12 +91,18 @@ typedef struct gicp_params {
     int32_t flags;          /* GICP_FLAG_* */
 } gicp_params;
 
-/* gicp_params.flags */
+/* gicp_params.flags.  Default (0): each Gauss-Newton iteration of all the
+ * call's problems is two launches (a linearisation launch over every chunk of
+ * every unfinished problem, then one solve workgroup per problem), max_it
+ * iterations per call; finished problems return at once. */
 enum {
-    /* Run each Gauss-Newton iteration as its own pair of kernel launches
-     * (linearise, then solve), max_it pairs per call, instead of the
-     * persistent work-queue kernel that runs every iteration in one launch. */
-    GICP_FLAG_MULTI_LAUNCH = 1
+    /* One problem at a time, with a linearise and a solve launch per
+     * iteration (the plain per-registration form; for comparison). */
+    GICP_FLAG_MULTI_LAUNCH = 1,
+    /* One persistent work-queue launch runs every iteration of every problem:
+     * workers pop chunks, the last chunk of an iteration solves and posts the
+     * problem's next iteration. */
+    GICP_FLAG_QUEUE = 2
 };
 
 /* One problem of a batched registration. */

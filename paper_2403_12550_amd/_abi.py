@@ -29,6 +29,7 @@ class Params(C.Structure):
 
 
 FLAG_MULTI_LAUNCH = 1
+FLAG_QUEUE = 2
 
 
 class Problem(C.Structure):

@@ -20,6 +20,7 @@ struct Buf {
 
 struct GridBufs {
     Buf keys_a, vals_a, keys_b, vals_b, scratch, spts, table;
+    const uint32_t* sorted_vals = nullptr;   // original indices in cell order (last build)
 };
 
 struct HipError {
@@ -71,17 +72,18 @@ struct gicp_ctx {
     int* d_err = nullptr;
     int* h_err = nullptr;
     GridBufs grid;
-    Buf covs, partials, kth;
+    Buf covs, partials, kth, ssrc, sscov, nn_prev, overflow;
     RegState* d_state = nullptr;     // [state_cap]
     RegState* h_state = nullptr;     // pinned [state_cap]
     ProbDev* d_probs = nullptr;      // [state_cap]
     ProbDev* h_probs = nullptr;      // pinned [state_cap]
     int state_cap = 0;
     QueueDev* d_queue = nullptr;
-    Buf items, arrive;
+    Buf items, arrive, chunk_prob;
     int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
     double queue_units = 0.0;        // source points x iterations of the last queue launch
+    std::vector<double> iter_units;  // per iteration: source points of the problems still running
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -139,7 +141,11 @@ void prof_collect(gicp_ctx* c, int iters_done) {
         check(hipEventElapsedTime(&ms, m.a, m.b));
         c->launches[m.group] += 1;
         c->ms[m.group] += ms;
-        c->units[m.group] += (m.iter == -2) ? c->queue_units : m.units;
+        double u = m.units;
+        if (m.iter == -2) u = c->queue_units;
+        else if (m.iter >= 0 && m.group == GICP_PROF_LINEARIZE && m.iter < (int)c->iter_units.size())
+            u = c->iter_units[m.iter];
+        c->units[m.group] += u;
     }
     c->marks.clear();
     c->ev_used = 0;
@@ -170,11 +176,13 @@ GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const float* xyz, int64_t n, in
     const float inv_h = 1.0f / h;
     const int pm = prof_open(ctx, GICP_PROF_GRID, (double)n, -1, s);
     check(launch_cell_keys(xyz, n, stride, inv_h, ka, va, ctx->d_err, s));
-    check(radix_sort_30(ka, va, kb, vb, n, scr, s));
+    uint32_t *ks = nullptr, *vs = nullptr;
+    check(radix_sort(ka, va, kb, vb, n, scr, s, &ks, &vs));
     check(launch_table_clear(table, cap, s));
-    check(launch_table_build(ka, va, n, xyz, stride, spts, table, cap - 1, s));
+    check(launch_table_build(ks, vs, n, xyz, stride, spts, table, cap - 1, s));
     prof_close(ctx, pm, s);
-    if (svals_keep) check(hipMemcpyAsync(svals_keep, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    gb.sorted_vals = vs;
+    if (svals_keep) check(hipMemcpyAsync(svals_keep, vs, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     GridView g;
     g.spts = spts;
     g.table = table;
@@ -280,7 +288,8 @@ int gicp_destroy(gicp_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (Buf* b : {&c->grid.keys_a, &c->grid.vals_a, &c->grid.keys_b, &c->grid.vals_b, &c->grid.scratch,
-                   &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth})
+                   &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
+                   &c->nn_prev, &c->overflow})
         release(*b);
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->d_state) (void)hipFree(c->d_state);
@@ -290,6 +299,7 @@ int gicp_destroy(gicp_ctx* c) {
     if (c->d_queue) (void)hipFree(c->d_queue);
     release(c->items);
     release(c->arrive);
+    release(c->chunk_prob);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_kth) (void)hipHostFree(c->h_kth);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -336,7 +346,9 @@ int gicp_knn(gicp_ctx* c, const float* pts, int64_t n, const float* queries, int
         hipStream_t s = (hipStream_t)stream;
         const float h = cell > 0.f ? cell : estimate_cell(c, pts, n, k, s);
         GridView g = build_grid(c, c->grid, pts, n, n, h, s);
-        check(launch_knn_query(g, queries, nq, k, r_max, idx, d2, c->d_err, s));
+        int32_t* ovf = ensure<int32_t>(c->overflow, nq + 1);
+        check(launch_fill_i32(ovf, 1, 0, s));
+        check(launch_knn_query(g, queries, nq, k, r_max, idx, d2, ovf, s));
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);
@@ -353,7 +365,9 @@ int gicp_covariances(gicp_ctx* c, const float* pts, int64_t n, int k, float cell
         const float h = cell > 0.f ? cell : estimate_cell(c, pts, n, k, s);
         GridView g = build_grid(c, c->grid, pts, n, n, h, s);
         const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)n, -1, s);
-        check(launch_knn_cov(g, pts, n, k, reg_mode, eps, covs, c->d_err, s));
+        int32_t* ovf = ensure<int32_t>(c->overflow, n + 1);
+        check(launch_fill_i32(ovf, 1, 0, s));
+        check(launch_knn_cov(g, pts, n, k, reg_mode, eps, covs, nullptr, ovf, s));
         prof_close(c, pm, s);
         return GICP_OK;
     } catch (const HipError& e) {
@@ -380,9 +394,7 @@ int gicp_map_build(gicp_ctx* c, const float* means, const float* covs, int64_t m
         check(hipMalloc(&mp->table, (size_t)cap * sizeof(uint4)));
         check(hipMalloc(&mp->scov, 2 * m * sizeof(float4)));
         build_grid(c, c->grid, means, m, m, h, s, mp->spts, mp->table);
-        // the sorted values (original indices) are still in grid.vals_a
-        check(launch_map_covs(static_cast<const uint32_t*>(c->grid.vals_a.p), m, covs, m, reg_mode, eps, mp->scov,
-                              c->d_err, s));
+        check(launch_map_covs(c->grid.sorted_vals, m, covs, m, reg_mode, eps, mp->scov, c->d_err, s));
         *out = mp;
         return GICP_OK;
     } catch (const HipError& e) {
@@ -436,18 +448,32 @@ bool valid_params(const gicp_params* prm) {
 // Returns the per-problem statuses in stats (never null here).
 void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm,
                    float* const* covs_out, double* poses, double* Hs, double* bs, gicp_stats* stats, hipStream_t s) {
-    // 1. source covariances where missing
-    int64_t need = 0;
-    for (int p = 0; p < nprob; ++p)
-        if (!probs[p].src_covs && !(covs_out && covs_out[p])) need += 6 * probs[p].n;
+    // 1. source covariances where missing; such problems are then linearised
+    // in their grid-cell order (sorted copies of the points and covariances)
+    int64_t need = 0, nsorted = 0, ntot = 0;
+    for (int p = 0; p < nprob; ++p) {
+        ntot += probs[p].n;
+        if (!probs[p].src_covs) {
+            nsorted += probs[p].n;
+            if (!(covs_out && covs_out[p])) need += 6 * probs[p].n;
+        }
+    }
     float* wcov = need ? ensure<float>(c->covs, need) : nullptr;
+    float4* wsrc = nsorted ? ensure<float4>(c->ssrc, nsorted) : nullptr;
+    float* wscov = nsorted ? ensure<float>(c->sscov, 6 * nsorted) : nullptr;
+    int32_t* nnprev = ensure<int32_t>(c->nn_prev, ntot);
     // size the grid workspace for the largest source up front (a reallocation
     // between problems would synchronise the device)
     int64_t nmax = 0;
     for (int p = 0; p < nprob; ++p)
         if (!probs[p].src_covs) nmax = std::max<int64_t>(nmax, probs[p].n);
-    if (nmax > 0) reserve_grid(c->grid, nmax);
+    if (nmax > 0) {
+        reserve_grid(c->grid, nmax);
+        ensure<int32_t>(c->overflow, nmax + 1);
+    }
     std::vector<const float*> scov(nprob);
+    std::vector<const float4*> ssrc(nprob, nullptr);
+    std::vector<const float*> sscov(nprob, nullptr);
     for (int p = 0; p < nprob; ++p) {
         const gicp_problem& P = probs[p];
         float* out = covs_out ? covs_out[p] : nullptr;
@@ -463,12 +489,19 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
             wcov += 6 * P.n;
         }
         const float h = prm->cell_src > 0.f ? prm->cell_src : estimate_cell(c, P.src, P.n, prm->k, s);
-        GridView g = build_grid(c, c->grid, P.src, P.n, P.n, h, s);
+        GridView g = build_grid(c, c->grid, P.src, P.n, P.n, h, s, wsrc);
         const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)P.n, -1, s);
-        check(launch_knn_cov(g, P.src, P.n, prm->k, prm->reg_mode, prm->eps, dst, c->d_err, s));
+        int32_t* ovf = static_cast<int32_t*>(c->overflow.p);
+        check(launch_fill_i32(ovf, 1, 0, s));
+        check(launch_knn_cov(g, P.src, P.n, prm->k, prm->reg_mode, prm->eps, dst, wscov, ovf, s));
         prof_close(c, pm, s);
         scov[p] = dst;
+        ssrc[p] = wsrc;
+        sscov[p] = wscov;
+        wsrc += P.n;
+        wscov += 6 * P.n;
     }
+    check(launch_fill_i32(nnprev, ntot, -1, s));
     // 2. states and problem descriptors
     ensure_states(c, nprob);
     int64_t chunks = 0;
@@ -489,6 +522,10 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         ProbDev& pd = c->h_probs[p];
         pd.src = P.src;
         pd.scov = scov[p];
+        pd.ssrc = ssrc[p];
+        pd.sscov = sscov[p];
+        pd.nn_prev = nnprev;
+        nnprev += P.n;
         pd.n = P.n;
         pd.nchunks = (int32_t)((P.n + kChunk - 1) / kChunk);
         pd.part0 = (int32_t)chunks;
@@ -498,6 +535,7 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     }
     check(hipMemcpyAsync(c->d_state, c->h_state, nprob * sizeof(RegState), hipMemcpyHostToDevice, s));
     // 3. Gauss-Newton
+    const bool queue = (prm->flags & GICP_FLAG_QUEUE) && !(prm->flags & GICP_FLAG_MULTI_LAUNCH);
     if (prm->max_it > 0) {
         if (prm->flags & GICP_FLAG_MULTI_LAUNCH) {
             for (int p = 0; p < nprob; ++p) {
@@ -506,14 +544,14 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
                 double* part = ensure<double>(c->partials, (size_t)nb * kNumAcc);
                 for (int it = 0; it < prm->max_it; ++it) {
                     const int pl = prof_open(c, GICP_PROF_LINEARIZE, (double)pd.n, nprob == 1 ? it : -3, s);
-                    check(launch_gn_linearize(pd.src, pd.scov, pd.n, pd.map, pd.st, part, nb, prm->precision, s));
+                    check(launch_gn_linearize(pd, part, nb, prm->precision, s));
                     prof_close(c, pl, s);
                     const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, nprob == 1 ? it : -3, s);
                     check(launch_gn_solve(part, nb, pd.st, s));
                     prof_close(c, ps, s);
                 }
             }
-        } else {
+        } else if (queue) {
             check(hipMemcpyAsync(c->d_probs, c->h_probs, nprob * sizeof(ProbDev), hipMemcpyHostToDevice, s));
             const uint64_t cap64 = (uint64_t)chunks * (uint64_t)prm->max_it;
             if (cap64 >= (1ull << 31)) throw HipError{hipErrorInvalidValue};
@@ -528,6 +566,23 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
             check(launch_gn_queue(c->d_probs, nprob, c->d_queue, items, cap, (uint32_t)chunks, arrive, part, workers,
                                   acc, s));
             prof_close(c, pq, s);
+        } else {
+            check(hipMemcpyAsync(c->d_probs, c->h_probs, nprob * sizeof(ProbDev), hipMemcpyHostToDevice, s));
+            int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, chunks);
+            double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
+            check(launch_chunk_map(c->d_probs, nprob, chunk_prob, s));
+            for (int it = 0; it < prm->max_it; ++it) {
+                // units: the work of a launch is only known after the run; the
+                // single-problem case marks its iterations, batches count all
+                const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, it, s);
+                check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision, true,
+                                                false, s));
+                prof_close(c, pl, s);
+                const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, it, s);
+                check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision, false,
+                                                true, s));
+                prof_close(c, ps, s);
+            }
         }
     }
     check(hipMemcpyAsync(c->h_state, c->d_state, nprob * sizeof(RegState), hipMemcpyDeviceToHost, s));
@@ -535,12 +590,19 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     check(hipMemcpyAsync(c->h_err + 1, &c->d_queue->error, sizeof(int), hipMemcpyDeviceToHost, s));
     check(hipStreamSynchronize(s));
     double units = 0.0;
-    int iters0 = c->h_state[0].iters;
-    for (int p = 0; p < nprob; ++p) units += (double)probs[p].n * c->h_state[p].iters;
+    int iters_max = 0;
+    c->iter_units.assign(std::max(prm->max_it, 0), 0.0);
+    for (int p = 0; p < nprob; ++p) {
+        const int it = c->h_state[p].iters;
+        units += (double)probs[p].n * it;
+        iters_max = std::max(iters_max, it);
+        for (int j = 0; j < it && j < (int)c->iter_units.size(); ++j) c->iter_units[j] += (double)probs[p].n;
+    }
     c->queue_units = units;
-    if (c->prof) prof_collect(c, nprob == 1 ? iters0 : 1 << 30);
+    const bool per_problem = (prm->flags & GICP_FLAG_MULTI_LAUNCH) && nprob > 1;
+    if (c->prof) prof_collect(c, per_problem ? (1 << 30) : iters_max);
     const bool nonfinite = (c->h_err[0] & kErrNonFinite) != 0;
-    const bool qerr = !(prm->flags & GICP_FLAG_MULTI_LAUNCH) && prm->max_it > 0 && c->h_err[1] != 0;
+    const bool qerr = queue && prm->max_it > 0 && c->h_err[1] != 0;
     if (nonfinite) {
         check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
         check(hipStreamSynchronize(s));

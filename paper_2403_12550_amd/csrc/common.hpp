@@ -10,9 +10,10 @@ namespace gicp {
 
 constexpr int kBlock = 256;           // threads per workgroup for the point kernels
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-constexpr int kCellBits = 10;         // wrapped cell coordinate bits per axis (30-bit keys)
+constexpr int kCellBits = 8;          // wrapped cell coordinate bits per axis (24-bit keys)
 constexpr uint32_t kCellMask = (1u << kCellBits) - 1u;
-constexpr int kMaxShell = 8;          // grid shells searched before the full-scan fallback
+constexpr int kMaxShell = 8;          // k-NN grid shells searched before the overflow pass
+constexpr int kMaxGateShells = 64;    // 1-NN: shells allowed for the gate to end the search
 constexpr int kNumAcc = 29;           // 21 unique H terms, 6 b terms, cost, inlier count
 
 // Error bits recorded on the device (context error word).
@@ -21,9 +22,9 @@ constexpr int kErrInexact = 2;
 
 // ---------------------------------------------------------------------------
 // Grid cells.  A point p lies in cell floor(p * inv_h) per axis; the cell key
-// packs the three cell coordinates modulo 1024 (10 bits each).  Wrapping
-// cannot break exactness: candidates are always ranked by their real
-// distance, and an aliased cell only adds far-away candidates.
+// packs the three cell coordinates modulo 256 (8 bits each).  Wrapping cannot
+// break exactness: candidates are always ranked by their real distance, and
+// an aliased cell (256 cells away) only adds far-away candidates.
 // ---------------------------------------------------------------------------
 struct Cell {
     int x, y, z;
@@ -42,8 +43,11 @@ __device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz) {
            (((uint32_t)cz & kCellMask) << (2 * kCellBits));
 }
 
+// Knuth's multiplicative hashing: the slot is the top log2(capacity) bits of
+// key * 2654435761 mod 2^32 (the low bits of the product would depend only on
+// the low bits of the key, i.e. only on x and part of y).  mask = capacity - 1.
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t mask) {
-    return (key * 2654435761u) & mask;  // Knuth multiplicative hashing
+    return (key * 2654435761u) >> (32 - __popc(mask));
 }
 
 // Cell table lookup: entry = {key, start, count, -}.  Returns count (0 if the

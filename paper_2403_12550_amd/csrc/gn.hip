@@ -13,6 +13,8 @@
 // the state done, later launches return immediately.
 #include <float.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -27,111 +29,98 @@ __device__ __forceinline__ void two_sum(float a, float b, float& t, float& err) 
     err = (a - (t - bp)) + (b - bp);
 }
 
+// Fixed-order sum of one column of the chunk's per-point values (n values at
+// stride `stride` in LDS), in the accumulation mode ACC:
+//   TWOSUM: FP32 compensated summation (two-sum of every addition, the
+//           compensations summed alongside), returned as s + c in FP64;
+//   FP32:   plain FP32 summation;
+//   FP64:   FP64 summation of the FP32 values.
 template <int ACC>
-struct Acc;
+__device__ __forceinline__ double column_sum(const float* col, int n, int stride) {
+    if (ACC == GICP_ACC_TWOSUM) {
+        float s = 0.f, c = 0.f;
+        for (int p = 0; p < n; ++p) {
+            float t, e;
+            two_sum(s, col[p * stride], t, e);
+            s = t;
+            c += e;
+        }
+        return (double)s + (double)c;
+    } else if (ACC == GICP_ACC_FP32) {
+        float s = 0.f;
+        for (int p = 0; p < n; ++p) s += col[p * stride];
+        return (double)s;
+    } else {
+        double s = 0.0;
+        for (int p = 0; p < n; ++p) s += (double)col[p * stride];
+        return s;
+    }
+}
 
-template <>
-struct Acc<GICP_ACC_TWOSUM> {
-    float s[kNumAcc], c[kNumAcc];
-    __device__ __forceinline__ void zero() {
+// Exact 1-NN of q among the map means within the gate, searched by a group of
+// kGroup consecutive lanes (all holding the same q): lane l of the group scans
+// every kGroup-th cell (nearest cells first, skipping cells whose distance
+// lower bound exceeds its best key so far or the gate), then the group takes
+// the minimum (FP32 key, original index) with shuffles.  Exactness is proven
+// on the group minimum from the block clearance; otherwise the next shell is
+// split the same way, and after kMaxShell shells the whole map is scanned.
+// Returns the sorted position of the nearest mean within the gate, or -1, on
+// every lane of the group.
+__device__ __forceinline__ void group_min(uint64_t& best, int32_t& pos) {
 #pragma unroll
-        for (int j = 0; j < kNumAcc; ++j) s[j] = c[j] = 0.f;
-    }
-    __device__ __forceinline__ void add(int j, float x) {
-        float t, e;
-        two_sum(s[j], x, t, e);
-        s[j] = t;
-        c[j] += e;
-    }
-    __device__ __forceinline__ void put(int j, float x) { s[j] = x; }
-    __device__ __forceinline__ void wave_reduce() {
-#pragma unroll
-        for (int j = 0; j < kNumAcc; ++j) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const float s2 = __shfl_xor(s[j], o, 64);
-                const float c2 = __shfl_xor(c[j], o, 64);
-                float t, e;
-                two_sum(s[j], s2, t, e);
-                s[j] = t;
-                c[j] = c[j] + c2 + e;
-            }
+    for (int o = 1; o < kGroup; o <<= 1) {
+        const uint64_t ob = __shfl_xor(best, o, 64);
+        const int32_t op = __shfl_xor(pos, o, 64);
+        if (ob < best) {
+            best = ob;
+            pos = op;
         }
     }
-    __device__ __forceinline__ double total(int j) const { return (double)s[j] + (double)c[j]; }
-};
+}
 
-template <>
-struct Acc<GICP_ACC_FP32> {
-    float s[kNumAcc];
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int j = 0; j < kNumAcc; ++j) s[j] = 0.f;
-    }
-    __device__ __forceinline__ void add(int j, float x) { s[j] += x; }
-    __device__ __forceinline__ void put(int j, float x) { s[j] = x; }
-    __device__ __forceinline__ void wave_reduce() {
-#pragma unroll
-        for (int j = 0; j < kNumAcc; ++j)
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
-    }
-    __device__ __forceinline__ double total(int j) const { return (double)s[j]; }
-};
-
-template <>
-struct Acc<GICP_ACC_FP64> {
-    double s[kNumAcc];
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int j = 0; j < kNumAcc; ++j) s[j] = 0.0;
-    }
-    __device__ __forceinline__ void add(int j, float x) { s[j] += (double)x; }
-    __device__ __forceinline__ void put(int j, float x) { s[j] = (double)x; }
-    __device__ __forceinline__ void wave_reduce() {
-#pragma unroll
-        for (int j = 0; j < kNumAcc; ++j)
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
-    }
-    __device__ __forceinline__ double total(int j) const { return s[j]; }
-};
-
-// Exact 1-NN of q among the map means within the gate; returns the sorted
-// position (or -1).  Ranking by (FP32 key, original index).  Cells are
-// visited nearest first and skipped when their distance lower bound exceeds
-// the best key so far (or the gate).
-__device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz) {
+// `hint` (a map position, or -1) is a candidate evaluated first, typically the
+// point's match of the previous iteration: with its key as the starting bound,
+// pruning skips nearly every cell, and the search stays exact.
+__device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz, int l, int32_t hint) {
     const GridView& g = m.g;
-    if (!finite3(qx, qy, qz)) return -1;
+    const bool fin = finite3(qx, qy, qz);
     uint64_t best = ~0ull;
     int32_t pos = -1;
-    const Cell c = cell_of(qx, qy, qz, g.inv_h);
+    if (fin && hint >= 0 && hint < g.n) {
+        const float4 p = g.spts[hint];
+        best = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
+        pos = hint;
+    }
+    const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, g.inv_h);
     const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
-    auto bound = [&]() {
-        return fminf(best == ~0ull ? FLT_MAX : __uint_as_float((uint32_t)(best >> 32)), m.r_max2);
-    };
     auto scan = [&](int cx, int cy, int cz) {
-        const float lb = cell_lower_bound2(qx, qy, qz, cx, cy, cz, g.h, slack);
-        if (cell_pruned(lb, bound())) return;
+        const float bound =
+            fminf(best == ~0ull ? FLT_MAX : __uint_as_float((uint32_t)(best >> 32)), m.r_max2);
+        if (cell_pruned(cell_lower_bound2(qx, qy, qz, cx, cy, cz, g.h, slack), bound)) return;
         uint32_t start = 0;
         const uint32_t cnt = cell_lookup(g.table, g.mask, cell_key(cx, cy, cz), start);
         for (uint32_t j = 0; j < cnt; ++j) {
             const float4 p = g.spts[start + j];
-            const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-            const uint64_t v = lex(d2, __float_as_uint(p.w));
+            const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
             if (v < best) {
                 best = v;
                 pos = (int32_t)(start + j);
             }
         }
     };
-    for (int j = 0; j < 27; ++j) {
-        int dx, dy, dz;
-        block_offset(j, dx, dy, dz);
-        scan(c.x + dx, c.y + dy, c.z + dz);
+    if (fin) {
+        for (int j = l; j < 27; j += kGroup) {
+            int dx, dy, dz;
+            block_offset(j, dx, dy, dz);
+            scan(c.x + dx, c.y + dy, c.z + dz);
+        }
     }
+    group_min(best, pos);
+    if (!fin) return -1;
     const float r_gate = m.r_max * 1.000001f + 1e-6f;
+    // shells needed for the gate to end the search (the full scan below is
+    // reached only when r_max exceeds kMaxGateShells cells)
+    const int max_shell = min(max(kMaxShell, (int)ceilf(r_gate * g.inv_h) + 1), kMaxGateShells);
     for (int R = 1;; ++R) {
         const float clr = block_clearance(qx, qy, qz, c, R, g.h);
         if (clr > 0.f) {
@@ -141,11 +130,11 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                 if (bk < clr * clr * (1.f - 1e-6f)) break;
             }
         }
-        if (R >= kMaxShell) {
-            // full scan (exact by construction)
+        if (R >= max_shell) {
+            // full scan (exact by construction), split across the group
             best = ~0ull;
             pos = -1;
-            for (int32_t j = 0; j < g.n; ++j) {
+            for (int32_t j = l; j < g.n; j += kGroup) {
                 const float4 p = g.spts[j];
                 const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
                 if (v < best) {
@@ -153,38 +142,62 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                     pos = j;
                 }
             }
+            group_min(best, pos);
             break;
         }
         const int S = R + 1;
+        int idx = 0;
         for (int dz = -S; dz <= S; ++dz)
             for (int dy = -S; dy <= S; ++dy)
                 for (int dx = -S; dx <= S; ++dx)
-                    if (max(max(abs(dx), abs(dy)), abs(dz)) == S) scan(c.x + dx, c.y + dy, c.z + dz);
+                    if (max(max(abs(dx), abs(dy)), abs(dz)) == S) {
+                        if ((idx & (kGroup - 1)) == l) scan(c.x + dx, c.y + dy, c.z + dz);
+                        ++idx;
+                    }
+        group_min(best, pos);
     }
     if (pos < 0) return -1;
     const float bk = __uint_as_float((uint32_t)(best >> 32));
     return (bk <= m.r_max2) ? pos : -1;
 }
 
-// Linearisation of one source point at the pose (R, t), accumulated into acc
-// (PUT: the lane's first and only point, stored instead of added).
-template <int ACC, bool PUT = false>
-__device__ __forceinline__ void linearize_point(const float* __restrict__ src, const float* __restrict__ scov,
-                                                int64_t n, int64_t i, const MapView& map, const float* R,
-                                                const float* t, Acc<ACC>& acc) {
-#define ACC_ADD(j, x) (PUT ? acc.put((j), (x)) : acc.add((j), (x)))
-    const float x = src[i], y = src[n + i], z = src[2 * n + i];
+// Linearisation of source point i at the pose (R, t), evaluated by a group of
+// kGroup lanes (lane l of the group): on return, v[0..29) holds the point's
+// 21 unique terms of J^T M J, the 6 of J^T M d, d^T M d and 1 (the inlier
+// count); the return value is false (and v untouched) when the point has no
+// correspondence within r_max or a singular combined covariance.
+// Point i of the problem's processing order: the grid-cell order when the
+// problem carries its sorted source (ssrc, sscov), else the caller's order.
+__device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, const float* R, const float* t,
+                                                float* v, int l) {
+    const int64_t n = P.n;
+    float x, y, z;
+    const float* cv;
+    if (P.ssrc) {
+        const float4 p4 = P.ssrc[i];
+        x = p4.x;
+        y = p4.y;
+        z = p4.z;
+        cv = P.sscov;
+    } else {
+        x = P.src[i];
+        y = P.src[n + i];
+        z = P.src[2 * n + i];
+        cv = P.scov;
+    }
     const float qx = R[0] * x + R[1] * y + R[2] * z + t[0];
     const float qy = R[3] * x + R[4] * y + R[5] * z + t[1];
     const float qz = R[6] * x + R[7] * y + R[8] * z + t[2];
-    const int32_t pos = nearest(map, qx, qy, qz);
-    if (pos < 0) return;
+    const MapView& map = P.map;
+    const int32_t pos = nearest(map, qx, qy, qz, l, P.nn_prev[i]);
+    if (l == 0) P.nn_prev[i] = pos;
+    if (pos < 0) return false;
     const float4 mu = map.g.spts[pos];
     const float4 ca = map.scov[2 * pos];
     const float4 cb = map.scov[2 * pos + 1];
     // source covariance rotated: A = R Cs, S = A R^T
-    const float c00 = scov[i], c01 = scov[n + i], c02 = scov[2 * n + i];
-    const float c11 = scov[3 * n + i], c12 = scov[4 * n + i], c22 = scov[5 * n + i];
+    const float c00 = cv[i], c01 = cv[n + i], c02 = cv[2 * n + i];
+    const float c11 = cv[3 * n + i], c12 = cv[4 * n + i], c22 = cv[5 * n + i];
     const float a00 = R[0] * c00 + R[1] * c01 + R[2] * c02;
     const float a01 = R[0] * c01 + R[1] * c11 + R[2] * c12;
     const float a02 = R[0] * c02 + R[1] * c12 + R[2] * c22;
@@ -205,7 +218,7 @@ __device__ __forceinline__ void linearize_point(const float* __restrict__ src, c
     const float k01 = s02 * s12 - s01 * s22;
     const float k02 = s01 * s12 - s02 * s11;
     const float det = s00 * k00 + s01 * k01 + s02 * k02;
-    if (!(det > 0.f)) return;
+    if (!(det > 0.f)) return false;
     const float id = 1.f / det;
     const float m00 = k00 * id, m01 = k01 * id, m02 = k02 * id;
     const float m11 = (s00 * s22 - s02 * s02) * id;
@@ -229,68 +242,63 @@ __device__ __forceinline__ void linearize_point(const float* __restrict__ src, c
     const float h12 = -qz * b02 + qx * b22;
     const float h22 = qy * b02 - qx * b12;
     // H_wv = -B^T, H_vv = M
-    ACC_ADD(0, h00); ACC_ADD(1, h01); ACC_ADD(2, h02);
-    ACC_ADD(3, -b00); ACC_ADD(4, -b10); ACC_ADD(5, -b20);
-    ACC_ADD(6, h11); ACC_ADD(7, h12);
-    ACC_ADD(8, -b01); ACC_ADD(9, -b11); ACC_ADD(10, -b21);
-    ACC_ADD(11, h22);
-    ACC_ADD(12, -b02); ACC_ADD(13, -b12); ACC_ADD(14, -b22);
-    ACC_ADD(15, m00); ACC_ADD(16, m01); ACC_ADD(17, m02);
-    ACC_ADD(18, m11); ACC_ADD(19, m12);
-    ACC_ADD(20, m22);
+    v[0] = h00; v[1] = h01; v[2] = h02;
+    v[3] = -b00; v[4] = -b10; v[5] = -b20;
+    v[6] = h11; v[7] = h12;
+    v[8] = -b01; v[9] = -b11; v[10] = -b21;
+    v[11] = h22;
+    v[12] = -b02; v[13] = -b12; v[14] = -b22;
+    v[15] = m00; v[16] = m01; v[17] = m02;
+    v[18] = m11; v[19] = m12;
+    v[20] = m22;
     // b = [ [q]x^T M d ; -M d ],  [q]x^T v = v x q
-    ACC_ADD(21, md1 * qz - md2 * qy);
-    ACC_ADD(22, md2 * qx - md0 * qz);
-    ACC_ADD(23, md0 * qy - md1 * qx);
-    ACC_ADD(24, -md0); ACC_ADD(25, -md1); ACC_ADD(26, -md2);
-    ACC_ADD(27, dx * md0 + dy * md1 + dz * md2);
-    ACC_ADD(28, 1.f);
-#undef ACC_ADD
+    v[21] = md1 * qz - md2 * qy;
+    v[22] = md2 * qx - md0 * qz;
+    v[23] = md0 * qy - md1 * qx;
+    v[24] = -md0; v[25] = -md1; v[26] = -md2;
+    v[27] = dx * md0 + dy * md1 + dz * md2;
+    v[28] = 1.f;
+    return true;
 }
 
-// Workgroup reduction of the accumulators into 29 FP64 values at out[0..29).
+// One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, four
+// lanes per point.  The group's first lane stores the point's 29 values in an
+// LDS row (zeros when it is not an inlier); threads 0..28 then sum one column
+// each over the 64 rows in a fixed order, and write the chunk's FP64 partial.
 template <int ACC>
-__device__ __forceinline__ void block_reduce(Acc<ACC>& acc, double* __restrict__ out) {
-    acc.wave_reduce();
-    __shared__ double s_w[kBlock / 64][kNumAcc];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
+__device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, const float* R, const float* t,
+                                                double* __restrict__ out) {
+    __shared__ float s_val[kChunk][kNumAcc + 1];
+    const int l = threadIdx.x & (kGroup - 1);
+    const int pt = threadIdx.x / kGroup;
+    const int64_t i = c * kChunk + pt;
+    float v[kNumAcc];
+    bool ok = false;
+    if (i < P.n) ok = linearize_point(P, i, R, t, v, l);
+    if (l == 0) {
 #pragma unroll
-        for (int j = 0; j < kNumAcc; ++j) s_w[wave][j] = acc.total(j);
+        for (int j = 0; j < kNumAcc; ++j) s_val[pt][j] = ok ? v[j] : 0.f;
     }
     __syncthreads();
-    if (threadIdx.x < kNumAcc) {
-        double v;
-        if (ACC == GICP_ACC_FP32) {
-            float f = 0.f;
-            for (int w = 0; w < kBlock / 64; ++w) f += (float)s_w[w][threadIdx.x];
-            v = (double)f;
-        } else {
-            v = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) v += s_w[w][threadIdx.x];
-        }
-        out[threadIdx.x] = v;
-    }
-
+    if (threadIdx.x < kNumAcc) out[threadIdx.x] = column_sum<ACC>(&s_val[0][threadIdx.x], kChunk, kNumAcc + 1);
     __syncthreads();
 }
 
 template <int ACC>
-__global__ __launch_bounds__(kBlock) void k_gn_linearize(const float* __restrict__ src,
-                                                         const float* __restrict__ scov, int64_t n, MapView map,
-                                                         const RegState* __restrict__ st,
-                                                         double* __restrict__ partials) {
+__global__ __launch_bounds__(kBlock) void k_gn_linearize(ProbDev P, double* __restrict__ partials) {
+    const RegState* st = P.st;
     if (st->done) return;
     float R[9], t[3];
 #pragma unroll
     for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
 #pragma unroll
     for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
-    Acc<ACC> acc;
-    acc.zero();
+    chunk_linearize<ACC>(P, blockIdx.x, R, t, partials + (int64_t)blockIdx.x * kNumAcc);
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        linearize_point<ACC>(src, scov, n, i, map, R, t, acc);
-    block_reduce<ACC>(acc, partials + (int64_t)blockIdx.x * kNumAcc);
+        p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -413,8 +421,8 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
 
 namespace {
 
-constexpr int kSolveThreads = 256;
-constexpr int kSolveParts = 8;
+constexpr int kSolveThreads = 1024;
+constexpr int kSolveParts = 32;
 
 }  // namespace
 
@@ -427,8 +435,10 @@ __device__ void solve_state(const double* __restrict__ partials, int nparts, Reg
     __shared__ double s_HL[72];
     const int acc = st->acc;
     const int t = threadIdx.x;
-    if (t < kNumAcc * kSolveParts) {
-        const int j = t / kSolveParts, p = t % kSolveParts;
+    // kNumAcc x kSolveParts strided partial sums, whatever the block size, so
+    // that every caller reduces in the same order
+    for (int q = t; q < kNumAcc * kSolveParts; q += blockDim.x) {
+        const int j = q / kSolveParts, p = q % kSolveParts;
         if (acc == GICP_ACC_FP32) {
             float f = 0.f;
             for (int b = p; b < nparts; b += kSolveParts) f += (float)partials[(int64_t)b * kNumAcc + j];
@@ -517,11 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_gn_queue(const ProbDev* __restrict__
         for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
 #pragma unroll
         for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
-        Acc<ACC> acc;
-        acc.zero();
-        const int64_t i = (int64_t)c * kChunk + threadIdx.x;
-        if (i < P.n) linearize_point<ACC, true>(P.src, P.scov, P.n, i, P.map, R, t, acc);
-        block_reduce<ACC>(acc, partials + ((int64_t)P.part0 + c) * kNumAcc);
+        chunk_linearize<ACC>(P, c, R, t, partials + ((int64_t)P.part0 + c) * kNumAcc);
         if (threadIdx.x == 0) {
             __threadfence();  // release this chunk's partial
             s_last = (atomicAdd(&arrive[p], 1u) == (uint32_t)P.nchunks - 1u) ? 1 : 0;
@@ -579,28 +585,67 @@ __global__ void k_queue_post(const ProbDev* __restrict__ probs, int nprob, uint3
         items[P.part0 + c] = (((uint32_t)p << kChunkBits) | (uint32_t)c) + 1u;
 }
 
+// ---------------------------------------------------------------------------
+// Batched iteration as two launches: one workgroup per chunk of every
+// problem (problems already retired return at once), then one workgroup per
+// problem for its solve.  Same chunking and summation order as the queue.
+// ---------------------------------------------------------------------------
+__global__ void k_chunk_map(const ProbDev* __restrict__ probs, int nprob, int32_t* __restrict__ chunk_prob) {
+    const int p = blockIdx.x;
+    if (p >= nprob) return;
+    const ProbDev P = probs[p];
+    for (int c = threadIdx.x; c < P.nchunks; c += blockDim.x) chunk_prob[P.part0 + c] = p;
+}
+
+template <int ACC>
+__global__ __launch_bounds__(kBlock) void k_gn_linearize_batch(const ProbDev* __restrict__ probs,
+                                                               const int32_t* __restrict__ chunk_prob,
+                                                               double* __restrict__ partials) {
+    const int b = blockIdx.x;
+    const int p = chunk_prob[b];
+    const ProbDev P = probs[p];
+    const RegState* st = P.st;
+    if (st->done) return;
+    float R[9], t[3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
+    chunk_linearize<ACC>(P, b - P.part0, R, t, partials + (int64_t)b * kNumAcc);
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev* __restrict__ probs,
+                                                                  const double* __restrict__ partials) {
+    const ProbDev P = probs[blockIdx.x];
+    if (P.st->done) return;
+    solve_state(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, P.st);
+}
+
 }  // namespace
 
 int gn_blocks(int64_t n) {
-    const int64_t b = (n + kBlock - 1) / kBlock;
-    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+    const int64_t b = (n + kChunk - 1) / kChunk;
+    return (int)(b < 1 ? 1 : b);
 }
 
-hipError_t launch_gn_linearize(const float* src, const float* scov, int64_t n, const MapView& map, RegState* st,
-                               double* partials, int nblocks, int acc, hipStream_t s) {
+hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks, int acc, hipStream_t s) {
     switch (acc) {
         case GICP_ACC_FP32:
-            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_FP32>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
-                               (const RegState*)st, partials);
+            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_FP32>, dim3(nblocks), dim3(kBlock), 0, s, pd, partials);
             break;
         case GICP_ACC_FP64:
-            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_FP64>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
-                               (const RegState*)st, partials);
+            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_FP64>, dim3(nblocks), dim3(kBlock), 0, s, pd, partials);
             break;
         default:
-            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_TWOSUM>, dim3(nblocks), dim3(kBlock), 0, s, src, scov, n, map,
-                               (const RegState*)st, partials);
+            hipLaunchKernelGGL(k_gn_linearize<GICP_ACC_TWOSUM>, dim3(nblocks), dim3(kBlock), 0, s, pd, partials);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t b = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)b), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
@@ -632,6 +677,32 @@ hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_
         default:
             hipLaunchKernelGGL(k_gn_queue<GICP_ACC_TWOSUM>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_map(const ProbDev* probs, int nprob, int32_t* chunk_prob, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_map, dim3(nprob), dim3(256), 0, s, probs, nprob, chunk_prob);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, const int32_t* chunk_prob, int64_t chunks,
+                                     double* partials, int acc, bool linearize, bool solve, hipStream_t s) {
+    if (linearize) {
+        switch (acc) {
+            case GICP_ACC_FP32:
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP32>, dim3((unsigned)chunks), dim3(kBlock), 0, s,
+                                   probs, chunk_prob, partials);
+                break;
+            case GICP_ACC_FP64:
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP64>, dim3((unsigned)chunks), dim3(kBlock), 0, s,
+                                   probs, chunk_prob, partials);
+                break;
+            default:
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_TWOSUM>, dim3((unsigned)chunks), dim3(kBlock), 0,
+                                   s, probs, chunk_prob, partials);
+        }
+    }
+    if (solve) hipLaunchKernelGGL(k_gn_solve_batch, dim3(nprob), dim3(kSolveThreads), 0, s, probs, partials);
     return hipGetLastError();
 }
 

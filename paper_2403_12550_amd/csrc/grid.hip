@@ -1,9 +1,10 @@
-// Uniform-grid spatial hash: cell keys, a stable LSD radix sort of 30-bit keys
-// (four 8-bit digit passes), and the open-addressing cell table.
+// Uniform-grid spatial hash: cell keys, a stable LSD radix sort of 24-bit keys
+// (three 8-bit digit passes), and the open-addressing cell table.
 //
-// Radix sort design for wave64: each pass is (1) a per-tile digit histogram,
-// (2) an exclusive scan over the digit-major [256][tiles] count matrix, and
-// (3) a stable scatter.  Within a tile, elements are processed in rounds of
+// Radix sort design for wave64: each pass is (1) a per-tile digit histogram
+// (tile-major [tiles][256]), (2) one 256-thread workgroup that walks the tiles
+// (coalesced) to form every (tile, digit) scatter offset, and (3) a stable
+// scatter.  Within a tile, elements are processed in rounds of
 // 256 (one per lane, in order); lanes holding the same digit are found with
 // eight wavefront ballots, their rank is the popcount of the lower lanes of
 // the match mask, and per-wave digit totals in LDS order the four waves.
@@ -20,15 +21,12 @@ namespace gicp {
 namespace {
 
 constexpr int kDigitBits = 8;
-constexpr int kPasses = 4;                     // 30-bit keys
+constexpr int kPasses = 3;                     // 24-bit keys
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kIpt = 4;                        // rounds (elements per thread) per tile
 constexpr int kTile = kSortThreads * kIpt;     // 1024
-constexpr int kScanThreads = 1024;
-constexpr int kScanIpt = 16;
-constexpr int kScanChunk = kScanThreads * kScanIpt;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const uint32_t lane = __lane_id();
@@ -61,85 +59,58 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t* __rest
         if (valid && (m & lanemask_lt()) == 0) atomicAdd(&s_hist[d], (uint32_t)__popcll(m));
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kDigits; i += kSortThreads) counts[(int64_t)i * ntiles + blockIdx.x] = s_hist[i];
+    for (int i = threadIdx.x; i < kDigits; i += kSortThreads) counts[(int64_t)blockIdx.x * kDigits + i] = s_hist[i];
 }
 
-// Block-wide exclusive scan of one value per thread (1024 threads).
-__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
+// Scatter offsets of one pass: offsets[t][d] = (number of keys with a digit
+// below d) + (number of keys with digit d in tiles before t).  One thread per
+// digit walks the tiles in order (coalesced over the digits), then the digit
+// totals are scanned across the workgroup.
+__global__ __launch_bounds__(kDigits) void k_rs_offsets(const uint32_t* __restrict__ counts, int ntiles,
+                                                       uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t s_tot[kDigits];
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+    constexpr int kB = 16;   // tiles whose counts are loaded together
+    int t0 = 0;
+    for (; t0 + kB <= ntiles; t0 += kB) {
+        uint32_t c[kB];
+#pragma unroll
+        for (int r = 0; r < kB; ++r) c[r] = counts[(int64_t)(t0 + r) * kDigits + d];
+#pragma unroll
+        for (int r = 0; r < kB; ++r) {
+            offsets[(int64_t)(t0 + r) * kDigits + d] = run;
+            run += c[r];
+        }
+    }
+    for (int t = t0; t < ntiles; ++t) {
+        const uint32_t c = counts[(int64_t)t * kDigits + d];
+        offsets[(int64_t)t * kDigits + d] = run;
+        run += c;
+    }
+    // exclusive scan of the digit totals (256 values, 4 waves)
+    const int lane = d & 63, wave = d >> 6;
+    uint32_t x = run;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    if (lane == 63) s_wave[wave] = x;
+    if (lane == 63) s_tot[wave] = x;
     __syncthreads();
-    if (threadIdx.x < 64) {
-        uint32_t w = threadIdx.x < kScanThreads / 64 ? s_wave[threadIdx.x] : 0u;
-        uint32_t z = w;
+    uint32_t base = x - run;
+    for (int w = 0; w < wave; ++w) base += s_tot[w];
+    __syncthreads();
+    if (base != 0u) {
+        int t = 0;
+        for (; t + kB <= ntiles; t += kB) {
+            uint32_t o[kB];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(z, o, 64);
-            if ((int)threadIdx.x >= o) z += y;
+            for (int r = 0; r < kB; ++r) o[r] = offsets[(int64_t)(t + r) * kDigits + d];
+#pragma unroll
+            for (int r = 0; r < kB; ++r) offsets[(int64_t)(t + r) * kDigits + d] = o[r] + base;
         }
-        if (threadIdx.x < kScanThreads / 64) s_wave[threadIdx.x] = z - w;  // exclusive wave offsets
-        if (threadIdx.x == kScanThreads / 64 - 1) s_wave[kScanThreads / 64] = z;
-    }
-    __syncthreads();
-    total = s_wave[kScanThreads / 64];
-    const uint32_t r = s_wave[wave] + x - v;
-    __syncthreads();
-    return r;
-}
-
-// Phase 1: sums of chunks of kScanChunk counts.
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t c,
-                                                              uint32_t* __restrict__ sums) {
-    __shared__ uint32_t s_wave[kScanThreads / 64 + 1];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanIpt;
-    uint32_t v = 0;
-#pragma unroll
-    for (int j = 0; j < kScanIpt; ++j)
-        if (base + j < c) v += in[base + j];
-    uint32_t total;
-    block_exscan(v, s_wave, total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// Phase 2/3: exclusive scan of chunks, each offset by the exclusive prefix of
-// the chunk sums (computed in-block from `sums`, nchunks <= 1024*16).
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in, int64_t c,
-                                                            const uint32_t* __restrict__ sums, int nchunks,
-                                                            uint32_t* __restrict__ out) {
-    __shared__ uint32_t s_wave[kScanThreads / 64 + 1];
-    __shared__ uint32_t s_off;
-    // offset of this chunk: sum of sums[0 .. blockIdx.x)
-    if (sums != nullptr) {
-        uint32_t v = 0;
-        for (int j = threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) v += sums[j];
-        uint32_t total;
-        block_exscan(v, s_wave, total);
-        if (threadIdx.x == 0) s_off = total;
-    } else if (threadIdx.x == 0) {
-        s_off = 0;
-    }
-    __syncthreads();
-    const uint32_t off = s_off;
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanIpt;
-    uint32_t loc[kScanIpt];
-    uint32_t v = 0;
-#pragma unroll
-    for (int j = 0; j < kScanIpt; ++j) {
-        loc[j] = (base + j < c) ? in[base + j] : 0u;
-        v += loc[j];
-    }
-    uint32_t total;
-    uint32_t run = block_exscan(v, s_wave, total) + off;
-#pragma unroll
-    for (int j = 0; j < kScanIpt; ++j) {
-        if (base + j < c) out[base + j] = run;
-        run += loc[j];
+        for (; t < ntiles; ++t) offsets[(int64_t)t * kDigits + d] += base;
     }
 }
 
@@ -152,7 +123,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __r
     __shared__ uint32_t s_base[kDigits];
     __shared__ uint32_t s_wcount[kSortWaves][kDigits];
     for (int i = threadIdx.x; i < kDigits; i += kSortThreads) {
-        s_base[i] = offsets[(int64_t)i * ntiles + blockIdx.x];
+        s_base[i] = offsets[(int64_t)blockIdx.x * kDigits + i];
 #pragma unroll
         for (int w = 0; w < kSortWaves; ++w) s_wcount[w][i] = 0;
     }
@@ -235,21 +206,17 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 size_t radix_scratch_bytes(int64_t n) {
     const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, kTile));
-    const int64_t c = ntiles * kDigits;
-    const int64_t nchunks = ceil_div(c, kScanChunk);
-    return (size_t)(2 * c + nchunks + 64) * sizeof(uint32_t);
+    return (size_t)(2 * ntiles * kDigits + 64) * sizeof(uint32_t);
 }
 
-hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
-                         void* scratch, hipStream_t s) {
+hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
+                      void* scratch, hipStream_t s, uint32_t** keys_out, uint32_t** vals_out) {
+    *keys_out = keys_a;
+    *vals_out = vals_a;
     if (n <= 0) return hipSuccess;
     const int ntiles = (int)ceil_div(n, kTile);
-    const int64_t c = (int64_t)ntiles * kDigits;
-    const int nchunks = (int)ceil_div(c, kScanChunk);
-    if (nchunks > kScanThreads * 64) return hipErrorInvalidValue;
     uint32_t* counts = static_cast<uint32_t*>(scratch);
-    uint32_t* offs = counts + c;
-    uint32_t* sums = offs + c;
+    uint32_t* offs = counts + (int64_t)ntiles * kDigits;
     uint32_t* kin = keys_a;
     uint32_t* vin = vals_a;
     uint32_t* kout = keys_b;
@@ -257,21 +224,14 @@ hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, u
     for (int pass = 0; pass < kPasses; ++pass) {
         const int shift = pass * kDigitBits;
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n, shift, ntiles, counts);
-        if (nchunks > 1) {
-            hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(kScanThreads), 0, s, counts, c, sums);
-            hipLaunchKernelGGL(k_scan_down, dim3(nchunks), dim3(kScanThreads), 0, s, counts, c,
-                               (const uint32_t*)sums, nchunks, offs);
-        } else {
-            hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, s, counts, c,
-                               (const uint32_t*)nullptr, 1, offs);
-        }
+        hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(kDigits), 0, s, (const uint32_t*)counts, ntiles, offs);
         hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, kin, vin, n, shift, ntiles,
                            (const uint32_t*)offs, kout, vout);
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
-    // an even number of passes leaves the result in (keys_a, vals_a)
-    static_assert(kPasses % 2 == 0, "pass parity");
+    *keys_out = kin;
+    *vals_out = vin;
     return hipGetLastError();
 }
 

@@ -65,36 +65,67 @@ __device__ __forceinline__ float prune_bound(const TopK<K>& top, float gate2) {
     return fminf(kth, gate2);
 }
 
-// Exact k-NN of q.  The 27-cell block is visited nearest cell first, and a
-// cell is skipped when its distance lower bound already exceeds the current
-// k-th key (or the gate).  Exactness is then proven from the block clearance;
-// otherwise the next shell of cells is visited (with the same pruning), and
-// after kMaxShell shells the whole cloud is scanned.
+// Exact k-NN of q by a group of kGroup consecutive lanes (lane l; all hold
+// q).  Each lane fills its own top-k from every kGroup-th cell of the 27-cell
+// block (nearest cells first; a cell is skipped when its distance lower bound
+// exceeds the lane's current k-th key or the gate).  The lanes publish their
+// sorted lists in `lists` (LDS, [kGroup][K]) and every lane merges the four
+// lists into the group's top-k, so the group continues converged.  Exactness
+// is then proven from the block clearance; the rare remaining cases scan the
+// next shells on the merged list, redundantly on the group's lanes.  Returns
+// false when kMaxShell shells did not prove the result exact: the caller then
+// hands the query to the overflow pass (a full scan by a whole workgroup).
 template <int K>
-__device__ __forceinline__ void knn_search(const GridView& g, float qx, float qy, float qz, int k, float gate2,
-                                           float r_gate, TopK<K>& top) {
+__device__ __forceinline__ bool knn_search(const GridView& g, float qx, float qy, float qz, int k, float gate2,
+                                           float r_gate, TopK<K>& top, int l, uint64_t* lists) {
     top.init(k);
-    if (!finite3(qx, qy, qz)) return;   // no neighbour has a finite distance
-    const Cell c = cell_of(qx, qy, qz, g.inv_h);
+    const bool fin = finite3(qx, qy, qz);   // a non-finite query has no neighbour with a finite distance
+    const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, g.inv_h);
     const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
-    for (int j = 0; j < 27; ++j) {
-        int dx, dy, dz;
-        block_offset(j, dx, dy, dz);
-        const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, g.h, slack);
-        if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-        scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+    if (fin) {
+        for (int j = l; j < 27; j += kGroup) {
+            int dx, dy, dz;
+            block_offset(j, dx, dy, dz);
+            const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, g.h, slack);
+            if (cell_pruned(lb, prune_bound(top, gate2))) continue;
+            scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+        }
     }
+    // publish and merge: the real entries of every list sit in [K - k, K)
+#pragma unroll
+    for (int j = 0; j < K; ++j) lists[l * K + j] = top.v[j];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int h0 = K - k, h1 = K - k, h2 = K - k, h3 = K - k;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j < K - k) continue;   // dummy slots keep their zero words
+        const uint64_t a0 = h0 < K ? lists[0 * K + h0] : ~0ull;
+        const uint64_t a1 = h1 < K ? lists[1 * K + h1] : ~0ull;
+        const uint64_t a2 = h2 < K ? lists[2 * K + h2] : ~0ull;
+        const uint64_t a3 = h3 < K ? lists[3 * K + h3] : ~0ull;
+        const uint64_t m01 = a0 < a1 ? a0 : a1;
+        const uint64_t m23 = a2 < a3 ? a2 : a3;
+        const uint64_t m = m01 < m23 ? m01 : m23;
+        top.v[j] = m;
+        if (m == a0) ++h0;
+        else if (m == a1) ++h1;
+        else if (m == a2) ++h2;
+        else ++h3;
+    }
+    if (!fin) return true;
     for (int R = 1;; ++R) {
         const float clr = block_clearance(qx, qy, qz, c, R, g.h);
         if (clr > 0.f) {
-            if (clr >= r_gate) return;   // every point within the gate has been seen
+            if (clr >= r_gate) return true;   // every point within the gate has been seen
             const uint64_t kth = top.v[K - 1];
             if (kth != ~0ull) {
                 const float kkey = __uint_as_float((uint32_t)(kth >> 32));
-                if (kkey < clr * clr * (1.f - 1e-6f)) return;
+                if (kkey < clr * clr * (1.f - 1e-6f)) return true;
             }
         }
-        if (R >= kMaxShell) break;
+        if (R >= kMaxShell) return false;   // left to the overflow pass
         const int S = R + 1;
         for (int dz = -S; dz <= S; ++dz)
             for (int dy = -S; dy <= S; ++dy)
@@ -104,13 +135,6 @@ __device__ __forceinline__ void knn_search(const GridView& g, float qx, float qy
                     if (cell_pruned(lb, prune_bound(top, gate2))) continue;
                     scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
                 }
-    }
-    // full scan (exact by construction)
-    top.init(k);
-    for (int32_t j = 0; j < g.n; ++j) {
-        const float4 p = g.spts[j];
-        const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
     }
 }
 
@@ -197,17 +221,19 @@ __device__ __forceinline__ void regularise(const Sym3& C, int mode, float eps, f
     out[3] = C.a11 * s; out[4] = C.a12 * s; out[5] = C.a22 * s;
 }
 
+// Threads per workgroup of the k-NN kernels: the lane lists take
+// threads * K * 8 bytes of LDS, kept within 64 KiB.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_knn_cov(GridView g, const float* __restrict__ xyz, int64_t stride,
-                                                    int k, int mode, float eps, float* __restrict__ covs,
-                                                    int64_t cstride) {
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.n) return;
-    const float4 q = g.spts[s];
-    const uint32_t orig = __float_as_uint(q.w);
-    TopK<K> top;
-    knn_search<K>(g, q.x, q.y, q.z, k, FLT_MAX, FLT_MAX, top);
-    // one pass, shifted by the query point (which is itself a neighbour)
+constexpr int knn_threads() {
+    return K <= 32 ? 256 : 128;
+}
+
+// Covariance of the k neighbours in `top` (shifted by the query point q, which
+// is itself a neighbour), regularised (Sec. 3.1).
+template <int K>
+__device__ __forceinline__ void cov_from_topk(const TopK<K>& top, int k, const float* __restrict__ xyz,
+                                              int64_t stride, float qx, float qy, float qz, int mode, float eps,
+                                              float out[6]) {
     float s1x = 0, s1y = 0, s1z = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
     int found = 0;
 #pragma unroll
@@ -216,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_knn_cov(GridView g, const float* __r
         // distance (non-finite input, reported through the error word)
         if (j >= K - k && top.v[j] != ~0ull) {
             const uint32_t id = (uint32_t)(top.v[j] & 0xFFFFFFFFu);
-            const float dx = xyz[id] - q.x, dy = xyz[stride + id] - q.y, dz = xyz[2 * stride + id] - q.z;
+            const float dx = xyz[id] - qx, dy = xyz[stride + id] - qy, dz = xyz[2 * stride + id] - qz;
             s1x += dx; s1y += dy; s1z += dz;
             sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
             syy += dy * dy; syz += dy * dz; szz += dz * dz;
@@ -232,21 +258,44 @@ __global__ __launch_bounds__(kBlock) void k_knn_cov(GridView g, const float* __r
     C.a11 = syy * ik - my * my;
     C.a12 = syz * ik - my * mz;
     C.a22 = szz * ik - mz * mz;
-    float out[6];
     regularise(C, mode, eps, out);
+}
+
+__device__ __forceinline__ void store_cov(const float out[6], float* __restrict__ covs, float* __restrict__ covs_sorted,
+                                          int64_t cstride, uint32_t orig, int32_t s) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) covs[(int64_t)c * cstride + orig] = out[c];
+    if (covs_sorted) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) covs_sorted[(int64_t)c * cstride + s] = out[c];
+    }
 }
 
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_knn_query(GridView g, const float* __restrict__ q, int64_t nq,
-                                                      int k, float gate2, float r_gate, int32_t* __restrict__ idx,
-                                                      float* __restrict__ d2) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    const float qx = q[i], qy = q[nq + i], qz = q[2 * nq + i];
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, const float* __restrict__ xyz,
+                                                              int64_t stride, int k, int mode, float eps,
+                                                              float* __restrict__ covs, int64_t cstride,
+                                                              float* __restrict__ covs_sorted,
+                                                              int32_t* __restrict__ overflow) {
+    constexpr int kT = knn_threads<K>();
+    __shared__ uint64_t s_lists[kT / kGroup][kGroup * K];
+    const int l = threadIdx.x & (kGroup - 1);
+    const int32_t s = blockIdx.x * (kT / kGroup) + threadIdx.x / kGroup;
+    if (s >= g.n) return;   // uniform over each lane group
+    const float4 q = g.spts[s];
     TopK<K> top;
-    knn_search<K>(g, qx, qy, qz, k, gate2, r_gate, top);
+    if (!knn_search<K>(g, q.x, q.y, q.z, k, FLT_MAX, FLT_MAX, top, l, s_lists[threadIdx.x / kGroup])) {
+        if (l == 0) overflow[1 + atomicAdd(&overflow[0], 1)] = s;
+        return;
+    }
+    float out[6];
+    cov_from_topk<K>(top, k, xyz, stride, q.x, q.y, q.z, mode, eps, out);
+    if (l == 0) store_cov(out, covs, covs_sorted, cstride, __float_as_uint(q.w), s);
+}
+
+template <int K>
+__device__ __forceinline__ void store_knn(const TopK<K>& top, int k, int64_t i, int32_t* __restrict__ idx,
+                                          float* __restrict__ d2) {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j >= K - k) {
@@ -256,6 +305,103 @@ __global__ __launch_bounds__(kBlock) void k_knn_query(GridView g, const float* _
             idx[o] = ok ? (int32_t)(v & 0xFFFFFFFFu) : -1;
             d2[o] = ok ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
         }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_query(GridView g, const float* __restrict__ q, int64_t nq,
+                                                                int k, float gate2, float r_gate,
+                                                                int32_t* __restrict__ idx, float* __restrict__ d2,
+                                                                int32_t* __restrict__ overflow) {
+    constexpr int kT = knn_threads<K>();
+    __shared__ uint64_t s_lists[kT / kGroup][kGroup * K];
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t i = (int64_t)blockIdx.x * (kT / kGroup) + threadIdx.x / kGroup;
+    if (i >= nq) return;   // uniform over each lane group
+    const float qx = q[i], qy = q[nq + i], qz = q[2 * nq + i];
+    TopK<K> top;
+    if (!knn_search<K>(g, qx, qy, qz, k, gate2, r_gate, top, l, s_lists[threadIdx.x / kGroup])) {
+        if (l == 0) overflow[1 + atomicAdd(&overflow[0], 1)] = (int32_t)i;
+        return;
+    }
+    if (l == 0) store_knn<K>(top, k, i, idx, d2);
+}
+
+// ---------------------------------------------------------------------------
+// Overflow pass: the queries whose k-NN could not be proven exact from the
+// grid shells.  One workgroup per query: every thread keeps the top-k of a
+// strided slice of the whole cloud, then the lists are merged pairwise in LDS
+// (log2(threads) rounds); thread 0 finishes the query.  Workgroups loop over
+// the overflow list, whose length is read on the device.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void full_scan_topk(const GridView& g, float qx, float qy, float qz, int k, float gate2,
+                                               TopK<K>& top, uint64_t* lists) {
+    top.init(k);
+    for (int32_t j = threadIdx.x; j < g.n; j += blockDim.x) {
+        const float4 p = g.spts[j];
+        const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
+        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+    }
+    for (int half = blockDim.x / 2; half >= 1; half >>= 1) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) lists[threadIdx.x * K + j] = top.v[j];
+        __syncthreads();
+        if (threadIdx.x < half) {
+            const uint64_t* a = lists + threadIdx.x * K;
+            const uint64_t* b = lists + (threadIdx.x + half) * K;
+            int ha = K - k, hb = K - k;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (j < K - k) continue;
+                const uint64_t va = ha < K ? a[ha] : ~0ull;
+                const uint64_t vb = hb < K ? b[hb] : ~0ull;
+                const bool ta = va <= vb;
+                top.v[j] = ta ? va : vb;
+                ha += ta ? 1 : 0;
+                hb += ta ? 0 : 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov_overflow(GridView g, const float* __restrict__ xyz,
+                                                                       int64_t stride, int k, int mode, float eps,
+                                                                       float* __restrict__ covs, int64_t cstride,
+                                                                       float* __restrict__ covs_sorted,
+                                                                       const int32_t* __restrict__ overflow) {
+    __shared__ uint64_t s_lists[knn_threads<K>() * K];
+    const int count = overflow[0];
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int32_t s = overflow[1 + e];
+        const float4 q = g.spts[s];
+        TopK<K> top;
+        full_scan_topk<K>(g, q.x, q.y, q.z, k, FLT_MAX, top, s_lists);
+        if (threadIdx.x == 0) {
+            float out[6];
+            cov_from_topk<K>(top, k, xyz, stride, q.x, q.y, q.z, mode, eps, out);
+            store_cov(out, covs, covs_sorted, cstride, __float_as_uint(q.w), s);
+        }
+        __syncthreads();
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_query_overflow(GridView g, const float* __restrict__ q,
+                                                                         int64_t nq, int k, float gate2,
+                                                                         int32_t* __restrict__ idx,
+                                                                         float* __restrict__ d2,
+                                                                         const int32_t* __restrict__ overflow) {
+    __shared__ uint64_t s_lists[knn_threads<K>() * K];
+    const int count = overflow[0];
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int64_t i = overflow[1 + e];
+        TopK<K> top;
+        full_scan_topk<K>(g, q[i], q[nq + i], q[2 * nq + i], k, gate2, top, s_lists);
+        if (threadIdx.x == 0) store_knn<K>(top, k, i, idx, d2);
+        __syncthreads();
     }
 }
 
@@ -331,47 +477,57 @@ __global__ void k_map_covs(const uint32_t* __restrict__ svals, int64_t m, const 
     scov[2 * i + 1] = make_float4(o[4], o[5], 0.f, 0.f);
 }
 
+constexpr int kOverflowBlocks = 64;
+
 template <int K>
 hipError_t knn_cov_t(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps, float* covs,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_knn_cov<K>, dim3((g.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, xyz, stride, k,
-                       mode, eps, covs, (int64_t)g.n);
+                     float* covs_sorted, int32_t* overflow, hipStream_t s) {
+    constexpr int kT = knn_threads<K>();
+    const int per = kT / kGroup;
+    hipLaunchKernelGGL(k_knn_cov<K>, dim3((g.n + per - 1) / per), dim3(kT), 0, s, g, xyz, stride, k, mode, eps,
+                       covs, (int64_t)g.n, covs_sorted, overflow);
+    hipLaunchKernelGGL(k_knn_cov_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, xyz, stride, k, mode, eps,
+                       covs, (int64_t)g.n, covs_sorted, (const int32_t*)overflow);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t knn_query_t(const GridView& g, const float* q, int64_t nq, int k, float gate2, float r_gate,
-                       int32_t* idx, float* d2, hipStream_t s) {
-    hipLaunchKernelGGL(k_knn_query<K>, dim3((unsigned)((nq + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, q, nq, k,
-                       gate2, r_gate, idx, d2);
+                       int32_t* idx, float* d2, int32_t* overflow, hipStream_t s) {
+    constexpr int kT = knn_threads<K>();
+    const int per = kT / kGroup;
+    hipLaunchKernelGGL(k_knn_query<K>, dim3((unsigned)((nq + per - 1) / per)), dim3(kT), 0, s, g, q, nq, k,
+                       gate2, r_gate, idx, d2, overflow);
+    hipLaunchKernelGGL(k_knn_query_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, q, nq, k, gate2, idx, d2,
+                       (const int32_t*)overflow);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_knn_cov(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps,
-                          float* covs, int* /*err*/, hipStream_t s) {
+                          float* covs, float* covs_sorted, int32_t* overflow, hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
-    if (k == 20) return knn_cov_t<20>(g, xyz, stride, k, mode, eps, covs, s);
-    if (k <= 8) return knn_cov_t<8>(g, xyz, stride, k, mode, eps, covs, s);
-    if (k <= 16) return knn_cov_t<16>(g, xyz, stride, k, mode, eps, covs, s);
-    if (k <= 32) return knn_cov_t<32>(g, xyz, stride, k, mode, eps, covs, s);
-    return knn_cov_t<64>(g, xyz, stride, k, mode, eps, covs, s);
+    if (k == 20) return knn_cov_t<20>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
+    if (k <= 8) return knn_cov_t<8>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
+    if (k <= 16) return knn_cov_t<16>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
+    if (k <= 32) return knn_cov_t<32>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
+    return knn_cov_t<64>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
 }
 
 hipError_t launch_knn_query(const GridView& g, const float* q, int64_t nq, int k, float r_max, int32_t* idx,
-                            float* d2, int* /*err*/, hipStream_t s) {
+                            float* d2, int32_t* overflow, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     float gate2 = FLT_MAX, r_gate = FLT_MAX;
     if (r_max > 0.f) {
         gate2 = r_max * r_max;
         r_gate = r_max * 1.000001f + 1e-6f;
     }
-    if (k == 20) return knn_query_t<20>(g, q, nq, k, gate2, r_gate, idx, d2, s);
-    if (k <= 8) return knn_query_t<8>(g, q, nq, k, gate2, r_gate, idx, d2, s);
-    if (k <= 16) return knn_query_t<16>(g, q, nq, k, gate2, r_gate, idx, d2, s);
-    if (k <= 32) return knn_query_t<32>(g, q, nq, k, gate2, r_gate, idx, d2, s);
-    return knn_query_t<64>(g, q, nq, k, gate2, r_gate, idx, d2, s);
+    if (k == 20) return knn_query_t<20>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    if (k <= 8) return knn_query_t<8>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    if (k <= 16) return knn_query_t<16>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    if (k <= 32) return knn_query_t<32>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    return knn_query_t<64>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
 }
 
 hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s) {

@@ -9,11 +9,11 @@
 namespace gicp {
 
 // Scratch the radix sort needs for n keys (bytes), and the launcher.  Sorts
-// 30-bit keys with their values stably, in place in (keys_a, vals_a), using
-// (keys_b, vals_b) as the ping-pong buffers.
+// 24-bit keys with their values stably, ping-ponging between the a and b
+// buffers; *keys_out / *vals_out receive the buffers that hold the result.
 size_t radix_scratch_bytes(int64_t n);
-hipError_t radix_sort_30(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
-                         int64_t n, void* scratch, hipStream_t s);
+hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
+                      void* scratch, hipStream_t s, uint32_t** keys_out, uint32_t** vals_out);
 
 // Grid over n points (SoA [3][stride]): keys + identity values.
 hipError_t launch_cell_keys(const float* xyz, int64_t n, int64_t stride, float inv_h,
@@ -34,11 +34,14 @@ struct GridView {
 };
 
 // Fused self k-NN + covariance + regularisation; covs SoA [6][n] in original order.
+// covs_sorted (nullable) additionally receives the covariances in grid order.
+// overflow: device int32 [1 + n], overflow[0] zeroed by the caller (queries
+// whose grid search could not be proven exact are finished by a second pass).
 hipError_t launch_knn_cov(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps,
-                          float* covs, int* err, hipStream_t s);
-// k-NN of arbitrary queries (SoA [3][nq]); idx/d2 row-major [nq][k].
+                          float* covs, float* covs_sorted, int32_t* overflow, hipStream_t s);
+// k-NN of arbitrary queries (SoA [3][nq]); idx/d2 row-major [nq][k]; overflow [1 + nq].
 hipError_t launch_knn_query(const GridView& g, const float* q, int64_t nq, int k, float r_max,
-                            int32_t* idx, float* d2, int* err, hipStream_t s);
+                            int32_t* idx, float* d2, int32_t* overflow, hipStream_t s);
 // k-th neighbour distance of `ns` evenly strided samples by brute force.
 hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s);
 // Map Gaussians: regularise covariances and store them in cell order (2 x float4 each).
@@ -73,6 +76,9 @@ struct MapView {
 struct ProbDev {
     const float* src;     // SoA [3][n]
     const float* scov;    // SoA [6][n]
+    const float4* ssrc;   // nullable: the source in grid-cell order (x, y, z, original index)
+    const float* sscov;   // with ssrc: the source covariances in that order, SoA [6][n]
+    int32_t* nn_prev;     // [n] map position matched by each point at the last iteration (-1: none)
     int64_t n;
     int32_t nchunks;      // ceil(n / kChunk)
     int32_t part0;        // first partial / item slot of the problem
@@ -89,16 +95,20 @@ struct QueueDev {
     uint32_t pad[3];
 };
 
-constexpr int kChunk = 256;          // source points per work item
+constexpr int kGroup = 4;            // lanes that search the correspondence of one point together
+constexpr int kChunk = kBlock / kGroup;   // source points per work item (64)
 constexpr int kChunkBits = 20;       // item = ((problem << 20) | chunk) + 1
 constexpr int kMaxProblems = 4096;
 
 int gn_blocks(int64_t n);
+hipError_t launch_chunk_map(const ProbDev* probs, int nprob, int32_t* chunk_prob, hipStream_t s);
+hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, const int32_t* chunk_prob, int64_t chunks,
+                                     double* partials, int acc, bool linearize, bool solve, hipStream_t s);
 int gn_queue_workers(int acc);
 hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_t* items, uint32_t cap,
                            uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, hipStream_t s);
-hipError_t launch_gn_linearize(const float* src, const float* scov, int64_t n, const MapView& map, RegState* st,
-                               double* partials, int nblocks, int acc, hipStream_t s);
+hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks, int acc, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
 
 }  // namespace gicp

@@ -41,18 +41,19 @@ def _c1(g, ctx, n=5000, seed=0):
 
 
 @pytest.mark.parametrize("acc", [0, 1, 2])
-def test_queue_equals_multi_launch(g, ctx, acc):
-    _say("queue_vs_multi", acc)
+def test_three_paths_agree(g, ctx, acc):
+    """Batched launches (default), per-registration launches and the work
+    queue evaluate the same expressions with the same chunking and summation
+    order: they agree bitwise."""
+    _say("paths", acc)
     pr, src, gm = _c1(g, ctx)
     a = ctx.register(src, gm, pr.init, g.params(max_it=30, precision=acc))
     b = ctx.register(src, gm, pr.init, g.params(max_it=30, precision=acc, flags=g.FLAG_MULTI_LAUNCH))
-    assert a.status == b.status == 0 and a.iters == b.iters == 30
-    # the two paths evaluate the same expressions with the same chunking and
-    # summation order; they are expected to agree bitwise, and must agree to
-    # rounding level
-    _say("  bitwise:", bool((a.pose == b.pose).all() and (a.H == b.H).all()))
-    assert np.allclose(a.pose, b.pose, rtol=0, atol=1e-12)
-    assert np.allclose(a.H, b.H, rtol=1e-12, atol=0)
+    q = ctx.register(src, gm, pr.init, g.params(max_it=30, precision=acc, flags=g.FLAG_QUEUE))
+    for r in (a, b, q):
+        assert r.status == 0 and r.iters == 30
+    for r in (b, q):
+        assert (a.pose == r.pose).all() and (a.H == r.H).all() and (a.b == r.b).all()
 
 
 def test_queue_early_exit_matches(g, ctx):
@@ -61,8 +62,9 @@ def test_queue_early_exit_matches(g, ctx):
     prm = dict(max_it=30, conv_rot=1e-6, conv_trans=1e-6)
     a = ctx.register(src, gm, pr.init, g.params(**prm))
     b = ctx.register(src, gm, pr.init, g.params(flags=g.FLAG_MULTI_LAUNCH, **prm))
-    assert a.converged and b.converged and a.iters == b.iters < 30
-    assert np.allclose(a.pose, b.pose, rtol=0, atol=1e-12)
+    q = ctx.register(src, gm, pr.init, g.params(flags=g.FLAG_QUEUE, **prm))
+    assert a.converged and b.converged and q.converged and a.iters == b.iters == q.iters < 30
+    assert (a.pose == b.pose).all() and (a.pose == q.pose).all()
 
 
 def _batch_problems(g, ctx, sizes, seed0=5000):
@@ -84,14 +86,16 @@ def _batch_problems(g, ctx, sizes, seed0=5000):
     return out
 
 
-def test_batch_equals_single(g, ctx):
-    _say("batch_vs_single")
+@pytest.mark.parametrize("flags", [0, 2])
+def test_batch_equals_single(g, ctx, flags):
+    _say("batch_vs_single", flags)
     sizes = [(2000, 30000), (7000, 60000), (15000, 20000), (300, 50000), (40000, 100000)]
     probs = _batch_problems(g, ctx, sizes)
-    prm = g.params(max_it=20, conv_rot=1e-6, conv_trans=1e-6, cell_src=0.0)
+    prm = g.params(max_it=20, conv_rot=1e-6, conv_trans=1e-6, cell_src=0.0, flags=flags)
     batch = ctx.register_batch([(p["src"], None, p["map"], np.eye(4)) for p in probs], prm)
     for p, rb in zip(probs, batch):
-        rs = ctx.register(p["src"], p["map"], np.eye(4), prm)
+        rs = ctx.register(p["src"], p["map"], np.eye(4), g.params(max_it=20, conv_rot=1e-6, conv_trans=1e-6,
+                                                                  flags=g.FLAG_MULTI_LAUNCH))
         assert rb.status == rs.status == 0
         assert rb.iters == rs.iters
         assert (rb.pose == rs.pose).all() and (rb.H == rs.H).all()
@@ -121,11 +125,12 @@ def test_batch_statuses(g, ctx):
     pr, src, gm = _c1(g, ctx, n=2000)
     far = np.eye(4)
     far[:3, 3] = [30, 0, 0]
-    res = ctx.register_batch([(src, None, gm, np.eye(4)), (src, None, gm, far), (src, None, gm, np.eye(4))],
-                             g.params(max_it=10))
-    assert [r.status for r in res] == [0, 3, 0]
-    assert res[1].iters == 1 and np.allclose(res[1].pose, far)
-    assert (res[0].pose == res[2].pose).all()
+    for flags in (0, 1, 2):
+        res = ctx.register_batch([(src, None, gm, np.eye(4)), (src, None, gm, far), (src, None, gm, np.eye(4))],
+                                 g.params(max_it=10, flags=flags))
+        assert [r.status for r in res] == [0, 3, 0]
+        assert res[1].iters == 1 and np.allclose(res[1].pose, far)
+        assert (res[0].pose == res[2].pose).all()
 
 
 def test_batch_arg_errors(g, ctx):

@@ -160,6 +160,25 @@ def test_covariances_cell_independent(g, ctx, cell):
     assert (a.view(np.uint32) == b.view(np.uint32)).all()
 
 
+def test_covariances_isolated_points_overflow(g, ctx):
+    """A few points far from a dense patch: their 20-NN radius exceeds the
+    searched grid shells, so they are finished by the overflow pass (a
+    workgroup-wide full scan); indices stay bit-exact and covariances match."""
+    _say("cov_overflow")
+    p, _ = synth.planar_patch(3000, 4, normal=(0.2, 0.1, 1.0))
+    rng = np.random.default_rng(4)
+    far = np.array([0.5, -0.3, 2.0]) + rng.uniform(1.5, 2.5, (6, 3))
+    pts = np.vstack([p, far]).astype(np.float32)
+    P = _soa(g, pts)
+    idx, d2 = ctx.knn(P, P, 20, cell=0.02)
+    ei, ek = ok.knn_bruteforce(pts, pts, 20)
+    assert (idx.cpu().numpy() == ei).all()
+    assert (d2.cpu().numpy().view(np.uint32) == ek.view(np.uint32)).all()
+    got = ctx.covariances(P, 20, cell=0.02, reg_mode=0).cpu().numpy().T
+    exp = oc.covariances(pts, 20, oc.REG_NONE)
+    assert _rel_frob(got, exp).max() < 1e-5
+
+
 def test_covariances_planar_patch(g, ctx):
     _say("cov_planar")
     p, n = synth.planar_patch(2000, 3, normal=(0, 0, 1))
