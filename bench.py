@@ -287,12 +287,14 @@ def run_c4(ctx, g, n_prob=64):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         n, ms, u = ctx.profile_read(0)
+        groups = {GROUP_NAMES[gid]: round(ctx.profile_read(gid)[1], 3) for gid in range(4)}
         ctx.profile(False)
         terr = max(float(np.linalg.norm(r.pose[:3, 3] - p.T_gt[:3, 3])) for r, p in zip(res, probs))
         out[name] = {"problems_per_s": round(n_prob / dt, 2), "ms": round(1e3 * dt, 3),
                      "mean_iterations": float(np.mean([r.iters for r in res])),
                      "statuses": sorted(set(int(r.status) for r in res)),
                      "linearize_GBps": round(72.0 * u / (ms * 1e-3) / 1e9, 2) if ms > 0 else None,
+                     "kernel_ms": groups,
                      "max_trans_err_vs_truth_m": terr}
         log(f"c4 {name}: {out[name]}")
     for gm in maps:

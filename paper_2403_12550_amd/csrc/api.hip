@@ -82,6 +82,8 @@ struct gicp_ctx {
     Buf items, arrive, chunk_prob;
     int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
+    Seg* h_segs = nullptr;           // pinned [kMaxSegments]
+    Buf segs;
     double queue_units = 0.0;        // source points x iterations of the last queue launch
     std::vector<double> iter_units;  // per iteration: source points of the problems still running
     // kernel timing
@@ -161,36 +163,49 @@ void reserve_grid(GridBufs& gb, int64_t n) {
     ensure<uint4>(gb.table, table_capacity(n));
 }
 
-// Builds the cell grid of n points (SoA, row stride `stride`) into `gb`.
-GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const float* xyz, int64_t n, int64_t stride, float h,
-                    hipStream_t s, float4* spts_out = nullptr, uint4* table_out = nullptr,
-                    uint32_t* svals_keep = nullptr) {
-    uint32_t* ka = ensure<uint32_t>(gb.keys_a, n);
-    uint32_t* va = ensure<uint32_t>(gb.vals_a, n);
-    uint32_t* kb = ensure<uint32_t>(gb.keys_b, n);
-    uint32_t* vb = ensure<uint32_t>(gb.vals_b, n);
-    void* scr = ensure<uint8_t>(gb.scratch, radix_scratch_bytes(n));
-    const uint32_t cap = table_capacity(n);
-    float4* spts = spts_out ? spts_out : ensure<float4>(gb.spts, n);
+// Builds the cell grid of the clouds of S (total points) into `gb`: keys,
+// radix sort (3 passes for one cloud, 4 when the cloud index is part of the
+// key), cell table and the points gathered into grid order.
+GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const SegSet& S, int64_t total, hipStream_t s,
+                    float4* spts_out = nullptr, uint4* table_out = nullptr) {
+    uint32_t* ka = ensure<uint32_t>(gb.keys_a, total);
+    uint32_t* va = ensure<uint32_t>(gb.vals_a, total);
+    uint32_t* kb = ensure<uint32_t>(gb.keys_b, total);
+    uint32_t* vb = ensure<uint32_t>(gb.vals_b, total);
+    void* scr = ensure<uint8_t>(gb.scratch, radix_scratch_bytes(total));
+    const uint32_t cap = table_capacity(total);
+    float4* spts = spts_out ? spts_out : ensure<float4>(gb.spts, total);
     uint4* table = table_out ? table_out : ensure<uint4>(gb.table, cap);
-    const float inv_h = 1.0f / h;
-    const int pm = prof_open(ctx, GICP_PROF_GRID, (double)n, -1, s);
-    check(launch_cell_keys(xyz, n, stride, inv_h, ka, va, ctx->d_err, s));
+    const int pm = prof_open(ctx, GICP_PROF_GRID, (double)total, -1, s);
+    check(launch_cell_keys(S, total, ka, va, ctx->d_err, s));
     uint32_t *ks = nullptr, *vs = nullptr;
-    check(radix_sort(ka, va, kb, vb, n, scr, s, &ks, &vs));
+    check(radix_sort(ka, va, kb, vb, total, S.count > 1 ? 4 : 3, scr, s, &ks, &vs));
     check(launch_table_clear(table, cap, s));
-    check(launch_table_build(ks, vs, n, xyz, stride, spts, table, cap - 1, s));
+    check(launch_table_build(ks, vs, total, S, spts, table, cap - 1, s));
     prof_close(ctx, pm, s);
     gb.sorted_vals = vs;
-    if (svals_keep) check(hipMemcpyAsync(svals_keep, vs, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     GridView g;
     g.spts = spts;
     g.table = table;
     g.mask = cap - 1;
-    g.n = (int32_t)n;
-    g.h = h;
-    g.inv_h = inv_h;
+    g.n = (int32_t)total;
+    g.h = S.one.h;
+    g.inv_h = S.one.inv_h;
     return g;
+}
+
+SegSet one_cloud(const float* xyz, int64_t n, float h, float* covs = nullptr, float* covs_sorted = nullptr) {
+    SegSet S;
+    S.one.xyz = xyz;
+    S.one.covs = covs;
+    S.one.covs_sorted = covs_sorted;
+    S.one.off = 0;
+    S.one.n = n;
+    S.one.h = h;
+    S.one.inv_h = 1.0f / h;
+    S.many = nullptr;
+    S.count = 1;
+    return S;
 }
 
 float estimate_cell(gicp_ctx* ctx, const float* xyz, int64_t n, int k, hipStream_t s) {
@@ -275,6 +290,7 @@ int gicp_create(gicp_ctx** out, int device) {
         check(hipMalloc(&c->d_queue, sizeof(QueueDev)));
         check(hipHostMalloc(&c->h_err, 256));
         check(hipHostMalloc(&c->h_kth, 256 * sizeof(float)));
+        check(hipHostMalloc(&c->h_segs, kMaxSegments * sizeof(Seg)));
         *out = c;
         return GICP_OK;
     } catch (const HipError& e) {
@@ -302,6 +318,8 @@ int gicp_destroy(gicp_ctx* c) {
     release(c->chunk_prob);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_kth) (void)hipHostFree(c->h_kth);
+    if (c->h_segs) (void)hipHostFree(c->h_segs);
+    release(c->segs);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return GICP_OK;
@@ -345,10 +363,11 @@ int gicp_knn(gicp_ctx* c, const float* pts, int64_t n, const float* queries, int
         check(hipSetDevice(c->device));
         hipStream_t s = (hipStream_t)stream;
         const float h = cell > 0.f ? cell : estimate_cell(c, pts, n, k, s);
-        GridView g = build_grid(c, c->grid, pts, n, n, h, s);
+        const SegSet S = one_cloud(pts, n, h);
+        GridView g = build_grid(c, c->grid, S, n, s);
         int32_t* ovf = ensure<int32_t>(c->overflow, nq + 1);
         check(launch_fill_i32(ovf, 1, 0, s));
-        check(launch_knn_query(g, queries, nq, k, r_max, idx, d2, ovf, s));
+        check(launch_knn_query(g, S.one, queries, nq, k, r_max, idx, d2, ovf, s));
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);
@@ -363,11 +382,12 @@ int gicp_covariances(gicp_ctx* c, const float* pts, int64_t n, int k, float cell
         check(hipSetDevice(c->device));
         hipStream_t s = (hipStream_t)stream;
         const float h = cell > 0.f ? cell : estimate_cell(c, pts, n, k, s);
-        GridView g = build_grid(c, c->grid, pts, n, n, h, s);
+        const SegSet S = one_cloud(pts, n, h, covs);
+        GridView g = build_grid(c, c->grid, S, n, s);
         const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)n, -1, s);
         int32_t* ovf = ensure<int32_t>(c->overflow, n + 1);
         check(launch_fill_i32(ovf, 1, 0, s));
-        check(launch_knn_cov(g, pts, n, k, reg_mode, eps, covs, nullptr, ovf, s));
+        check(launch_knn_cov(g, S, k, reg_mode, eps, ovf, s));
         prof_close(c, pm, s);
         return GICP_OK;
     } catch (const HipError& e) {
@@ -393,7 +413,7 @@ int gicp_map_build(gicp_ctx* c, const float* means, const float* covs, int64_t m
         check(hipMalloc(&mp->spts, m * sizeof(float4)));
         check(hipMalloc(&mp->table, (size_t)cap * sizeof(uint4)));
         check(hipMalloc(&mp->scov, 2 * m * sizeof(float4)));
-        build_grid(c, c->grid, means, m, m, h, s, mp->spts, mp->table);
+        build_grid(c, c->grid, one_cloud(means, m, h), m, s, mp->spts, mp->table);
         check(launch_map_covs(c->grid.sorted_vals, m, covs, m, reg_mode, eps, mp->scov, c->d_err, s));
         *out = mp;
         return GICP_OK;
@@ -464,9 +484,18 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     int32_t* nnprev = ensure<int32_t>(c->nn_prev, ntot);
     // size the grid workspace for the largest source up front (a reallocation
     // between problems would synchronise the device)
-    int64_t nmax = 0;
-    for (int p = 0; p < nprob; ++p)
-        if (!probs[p].src_covs) nmax = std::max<int64_t>(nmax, probs[p].n);
+    int64_t nmax = 0, run = 0;
+    int in_group = 0;
+    for (int p = 0; p < nprob; ++p) {
+        if (probs[p].src_covs) continue;
+        if (in_group == kMaxSegments) {
+            in_group = 0;
+            run = 0;
+        }
+        run += probs[p].n;
+        ++in_group;
+        nmax = std::max(nmax, run);
+    }
     if (nmax > 0) {
         reserve_grid(c->grid, nmax);
         ensure<int32_t>(c->overflow, nmax + 1);
@@ -474,32 +503,65 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     std::vector<const float*> scov(nprob);
     std::vector<const float4*> ssrc(nprob, nullptr);
     std::vector<const float*> sscov(nprob, nullptr);
+    // problems with caller covariances keep the caller's order
     for (int p = 0; p < nprob; ++p) {
         const gicp_problem& P = probs[p];
         float* out = covs_out ? covs_out[p] : nullptr;
-        if (P.src_covs) {
-            scov[p] = P.src_covs;
-            if (out && out != P.src_covs)
-                check(hipMemcpyAsync(out, P.src_covs, 6 * P.n * sizeof(float), hipMemcpyDeviceToDevice, s));
-            continue;
+        if (!P.src_covs) continue;
+        scov[p] = P.src_covs;
+        if (out && out != P.src_covs)
+            check(hipMemcpyAsync(out, P.src_covs, 6 * P.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    // the others: one segmented grid and one k-NN covariance launch per group
+    // of up to kMaxSegments sources
+    std::vector<int> todo;
+    for (int p = 0; p < nprob; ++p)
+        if (!probs[p].src_covs) todo.push_back(p);
+    for (size_t g0 = 0; g0 < todo.size(); g0 += kMaxSegments) {
+        const size_t g1 = std::min(todo.size(), g0 + kMaxSegments);
+        const int cnt = (int)(g1 - g0);
+        int64_t total = 0;
+        for (size_t q = g0; q < g1; ++q) {
+            const int p = todo[q];
+            const gicp_problem& P = probs[p];
+            float* out = covs_out ? covs_out[p] : nullptr;
+            float* dst = out;
+            if (!dst) {
+                dst = wcov;
+                wcov += 6 * P.n;
+            }
+            const float h = prm->cell_src > 0.f ? prm->cell_src : estimate_cell(c, P.src, P.n, prm->k, s);
+            Seg& sg = c->h_segs[q - g0];
+            sg.xyz = P.src;
+            sg.covs = dst;
+            sg.covs_sorted = wscov + 6 * total;
+            sg.off = total;
+            sg.n = P.n;
+            sg.h = h;
+            sg.inv_h = 1.0f / h;
+            scov[p] = dst;
+            ssrc[p] = wsrc + total;
+            sscov[p] = wscov + 6 * total;
+            total += P.n;
         }
-        float* dst = out;
-        if (!dst) {
-            dst = wcov;
-            wcov += 6 * P.n;
+        SegSet S;
+        S.one = c->h_segs[0];
+        S.count = cnt;
+        S.many = nullptr;
+        if (cnt > 1) {
+            Seg* dsegs = ensure<Seg>(c->segs, kMaxSegments);
+            check(hipMemcpyAsync(dsegs, c->h_segs, cnt * sizeof(Seg), hipMemcpyHostToDevice, s));
+            S.many = dsegs;
         }
-        const float h = prm->cell_src > 0.f ? prm->cell_src : estimate_cell(c, P.src, P.n, prm->k, s);
-        GridView g = build_grid(c, c->grid, P.src, P.n, P.n, h, s, wsrc);
-        const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)P.n, -1, s);
+        GridView g = build_grid(c, c->grid, S, total, s, wsrc);
+        const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)total, -1, s);
         int32_t* ovf = static_cast<int32_t*>(c->overflow.p);
         check(launch_fill_i32(ovf, 1, 0, s));
-        check(launch_knn_cov(g, P.src, P.n, prm->k, prm->reg_mode, prm->eps, dst, wscov, ovf, s));
+        check(launch_knn_cov(g, S, prm->k, prm->reg_mode, prm->eps, ovf, s));
         prof_close(c, pm, s);
-        scov[p] = dst;
-        ssrc[p] = wsrc;
-        sscov[p] = wscov;
-        wsrc += P.n;
-        wscov += 6 * P.n;
+        wsrc += total;
+        wscov += 6 * total;
+        if (g1 < todo.size()) check(hipStreamSynchronize(s));   // the staging array is reused
     }
     check(launch_fill_i32(nnprev, ntot, -1, s));
     // 2. states and problem descriptors

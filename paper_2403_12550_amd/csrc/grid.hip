@@ -21,7 +21,6 @@ namespace gicp {
 namespace {
 
 constexpr int kDigitBits = 8;
-constexpr int kPasses = 3;                     // 24-bit keys
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
@@ -159,14 +158,17 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __r
     }
 }
 
-__global__ void k_cell_keys(const float* __restrict__ xyz, int64_t n, int64_t stride, float inv_h,
-                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int* err) {
+__global__ void k_cell_keys(SegSet S, int64_t total, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            int* err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float x = xyz[i], y = xyz[stride + i], z = xyz[2 * stride + i];
+    if (i >= total) return;
+    const int p = S.find(i);
+    const Seg sg = S.get(p);
+    const int64_t j = i - sg.off;
+    const float x = sg.xyz[j], y = sg.xyz[sg.n + j], z = sg.xyz[2 * sg.n + j];
     if (!finite3(x, y, z)) atomicOr(err, kErrNonFinite);
-    const Cell c = cell_of(x, y, z, inv_h);
-    keys[i] = cell_key(c.x, c.y, c.z);
+    const Cell c = cell_of(x, y, z, sg.inv_h);
+    keys[i] = ((uint32_t)p << (3 * kCellBits)) | cell_key(c.x, c.y, c.z);
     vals[i] = (uint32_t)i;
 }
 
@@ -175,18 +177,19 @@ __global__ void k_table_clear(uint4* __restrict__ table, uint32_t cap) {
     if (i < cap) table[i] = make_uint4(kEmptyKey, 0u, 0u, 0u);
 }
 
-__global__ void k_table_build(const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals, int64_t n,
-                              const float* __restrict__ xyz, int64_t stride, float4* __restrict__ spts,
-                              uint4* __restrict__ table, uint32_t mask) {
+__global__ void k_table_build(const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals, int64_t total,
+                              SegSet S, float4* __restrict__ spts, uint4* __restrict__ table, uint32_t mask) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= total) return;
     uint32_t v = svals[i];
-    if (v >= (uint64_t)n) v = 0;   // always a permutation; guards the gather
-    spts[i] = make_float4(xyz[v], xyz[stride + v], xyz[2 * stride + v], __uint_as_float(v));
+    if (v >= (uint64_t)total) v = 0;   // always a permutation; guards the gather
+    const Seg sg = S.get(S.find(v));
+    const int64_t j = (int64_t)v - sg.off;
+    spts[i] = make_float4(sg.xyz[j], sg.xyz[sg.n + j], sg.xyz[2 * sg.n + j], __uint_as_float((uint32_t)j));
     const uint32_t key = skeys[i];
     if (i == 0 || skeys[i - 1] != key) {
         uint32_t cnt = 1;
-        while (i + cnt < n && skeys[i + cnt] == key) ++cnt;
+        while (i + cnt < total && skeys[i + cnt] == key) ++cnt;
         uint32_t s = hash_slot(key, mask);
         while (true) {
             const uint32_t prev = atomicCAS(&table[s].x, kEmptyKey, key);
@@ -210,7 +213,7 @@ size_t radix_scratch_bytes(int64_t n) {
 }
 
 hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
-                      void* scratch, hipStream_t s, uint32_t** keys_out, uint32_t** vals_out) {
+                      int passes, void* scratch, hipStream_t s, uint32_t** keys_out, uint32_t** vals_out) {
     *keys_out = keys_a;
     *vals_out = vals_a;
     if (n <= 0) return hipSuccess;
@@ -221,7 +224,7 @@ hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint
     uint32_t* vin = vals_a;
     uint32_t* kout = keys_b;
     uint32_t* vout = vals_b;
-    for (int pass = 0; pass < kPasses; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * kDigitBits;
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n, shift, ntiles, counts);
         hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(kDigits), 0, s, (const uint32_t*)counts, ntiles, offs);
@@ -235,11 +238,10 @@ hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint
     return hipGetLastError();
 }
 
-hipError_t launch_cell_keys(const float* xyz, int64_t n, int64_t stride, float inv_h, uint32_t* keys,
-                            uint32_t* vals, int* err, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cell_keys, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, xyz, n, stride, inv_h, keys,
-                       vals, err);
+hipError_t launch_cell_keys(const SegSet& S, int64_t total, uint32_t* keys, uint32_t* vals, int* err,
+                            hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_keys, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, S, total, keys, vals, err);
     return hipGetLastError();
 }
 
@@ -248,11 +250,11 @@ hipError_t launch_table_clear(uint4* table, uint32_t cap, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int64_t n, const float* xyz,
-                              int64_t stride, float4* spts, uint4* table, uint32_t mask, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_table_build, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, skeys, svals, n, xyz,
-                       stride, spts, table, mask);
+hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int64_t total, const SegSet& S,
+                              float4* spts, uint4* table, uint32_t mask, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_table_build, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, skeys, svals, total, S,
+                       spts, table, mask);
     return hipGetLastError();
 }
 

@@ -76,19 +76,20 @@ __device__ __forceinline__ float prune_bound(const TopK<K>& top, float gate2) {
 // false when kMaxShell shells did not prove the result exact: the caller then
 // hands the query to the overflow pass (a full scan by a whole workgroup).
 template <int K>
-__device__ __forceinline__ bool knn_search(const GridView& g, float qx, float qy, float qz, int k, float gate2,
-                                           float r_gate, TopK<K>& top, int l, uint64_t* lists) {
+__device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv_h, uint32_t prefix, float qx,
+                                           float qy, float qz, int k, float gate2, float r_gate, TopK<K>& top, int l,
+                                           uint64_t* lists) {
     top.init(k);
     const bool fin = finite3(qx, qy, qz);   // a non-finite query has no neighbour with a finite distance
-    const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, g.inv_h);
-    const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
+    const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, inv_h);
+    const float slack = cell_slack(qx, qy, qz, kMaxShell, h);
     if (fin) {
         for (int j = l; j < 27; j += kGroup) {
             int dx, dy, dz;
             block_offset(j, dx, dy, dz);
-            const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, g.h, slack);
+            const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
             if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-            scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+            scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
         }
     }
     // publish and merge: the real entries of every list sit in [K - k, K)
@@ -116,7 +117,7 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float qx, float qy
     }
     if (!fin) return true;
     for (int R = 1;; ++R) {
-        const float clr = block_clearance(qx, qy, qz, c, R, g.h);
+        const float clr = block_clearance(qx, qy, qz, c, R, h);
         if (clr > 0.f) {
             if (clr >= r_gate) return true;   // every point within the gate has been seen
             const uint64_t kth = top.v[K - 1];
@@ -131,9 +132,9 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float qx, float qy
             for (int dy = -S; dy <= S; ++dy)
                 for (int dx = -S; dx <= S; ++dx) {
                     if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
-                    const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, g.h, slack);
+                    const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
                     if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-                    scan_cell<K>(g, cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+                    scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
                 }
     }
 }
@@ -272,25 +273,25 @@ __device__ __forceinline__ void store_cov(const float out[6], float* __restrict_
 }
 
 template <int K>
-__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, const float* __restrict__ xyz,
-                                                              int64_t stride, int k, int mode, float eps,
-                                                              float* __restrict__ covs, int64_t cstride,
-                                                              float* __restrict__ covs_sorted,
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, SegSet S, int k, int mode, float eps,
                                                               int32_t* __restrict__ overflow) {
     constexpr int kT = knn_threads<K>();
     __shared__ uint64_t s_lists[kT / kGroup][kGroup * K];
     const int l = threadIdx.x & (kGroup - 1);
     const int32_t s = blockIdx.x * (kT / kGroup) + threadIdx.x / kGroup;
     if (s >= g.n) return;   // uniform over each lane group
+    const int p = S.find(s);
+    const Seg sg = S.get(p);
     const float4 q = g.spts[s];
     TopK<K> top;
-    if (!knn_search<K>(g, q.x, q.y, q.z, k, FLT_MAX, FLT_MAX, top, l, s_lists[threadIdx.x / kGroup])) {
+    if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, FLT_MAX, FLT_MAX, top,
+                       l, s_lists[threadIdx.x / kGroup])) {
         if (l == 0) overflow[1 + atomicAdd(&overflow[0], 1)] = s;
         return;
     }
     float out[6];
-    cov_from_topk<K>(top, k, xyz, stride, q.x, q.y, q.z, mode, eps, out);
-    if (l == 0) store_cov(out, covs, covs_sorted, cstride, __float_as_uint(q.w), s);
+    cov_from_topk<K>(top, k, sg.xyz, sg.n, q.x, q.y, q.z, mode, eps, out);
+    if (l == 0) store_cov(out, sg.covs, sg.covs_sorted, sg.n, __float_as_uint(q.w), (int32_t)(s - sg.off));
 }
 
 template <int K>
@@ -309,9 +310,10 @@ __device__ __forceinline__ void store_knn(const TopK<K>& top, int k, int64_t i, 
 }
 
 template <int K>
-__global__ __launch_bounds__(knn_threads<K>()) void k_knn_query(GridView g, const float* __restrict__ q, int64_t nq,
-                                                                int k, float gate2, float r_gate,
-                                                                int32_t* __restrict__ idx, float* __restrict__ d2,
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_query(GridView g, float h, float inv_h,
+                                                                const float* __restrict__ q, int64_t nq, int k,
+                                                                float gate2, float r_gate, int32_t* __restrict__ idx,
+                                                                float* __restrict__ d2,
                                                                 int32_t* __restrict__ overflow) {
     constexpr int kT = knn_threads<K>();
     __shared__ uint64_t s_lists[kT / kGroup][kGroup * K];
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_query(GridView g, cons
     if (i >= nq) return;   // uniform over each lane group
     const float qx = q[i], qy = q[nq + i], qz = q[2 * nq + i];
     TopK<K> top;
-    if (!knn_search<K>(g, qx, qy, qz, k, gate2, r_gate, top, l, s_lists[threadIdx.x / kGroup])) {
+    if (!knn_search<K>(g, h, inv_h, 0u, qx, qy, qz, k, gate2, r_gate, top, l, s_lists[threadIdx.x / kGroup])) {
         if (l == 0) overflow[1 + atomicAdd(&overflow[0], 1)] = (int32_t)i;
         return;
     }
@@ -335,10 +337,10 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_query(GridView g, cons
 // the overflow list, whose length is read on the device.
 // ---------------------------------------------------------------------------
 template <int K>
-__device__ __forceinline__ void full_scan_topk(const GridView& g, float qx, float qy, float qz, int k, float gate2,
-                                               TopK<K>& top, uint64_t* lists) {
+__device__ __forceinline__ void full_scan_topk(const GridView& g, int64_t lo, int64_t hi, float qx, float qy,
+                                               float qz, int k, float gate2, TopK<K>& top, uint64_t* lists) {
     top.init(k);
-    for (int32_t j = threadIdx.x; j < g.n; j += blockDim.x) {
+    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
         const float4 p = g.spts[j];
         const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
         if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
@@ -367,22 +369,22 @@ __device__ __forceinline__ void full_scan_topk(const GridView& g, float qx, floa
 }
 
 template <int K>
-__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov_overflow(GridView g, const float* __restrict__ xyz,
-                                                                       int64_t stride, int k, int mode, float eps,
-                                                                       float* __restrict__ covs, int64_t cstride,
-                                                                       float* __restrict__ covs_sorted,
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov_overflow(GridView g, SegSet S, int k, int mode,
+                                                                       float eps,
                                                                        const int32_t* __restrict__ overflow) {
     __shared__ uint64_t s_lists[knn_threads<K>() * K];
     const int count = overflow[0];
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
         const int32_t s = overflow[1 + e];
+        const int p = S.find(s);
+        const Seg sg = S.get(p);
         const float4 q = g.spts[s];
         TopK<K> top;
-        full_scan_topk<K>(g, q.x, q.y, q.z, k, FLT_MAX, top, s_lists);
+        full_scan_topk<K>(g, sg.off, sg.off + sg.n, q.x, q.y, q.z, k, FLT_MAX, top, s_lists);
         if (threadIdx.x == 0) {
             float out[6];
-            cov_from_topk<K>(top, k, xyz, stride, q.x, q.y, q.z, mode, eps, out);
-            store_cov(out, covs, covs_sorted, cstride, __float_as_uint(q.w), s);
+            cov_from_topk<K>(top, k, sg.xyz, sg.n, q.x, q.y, q.z, mode, eps, out);
+            store_cov(out, sg.covs, sg.covs_sorted, sg.n, __float_as_uint(q.w), (int32_t)(s - sg.off));
         }
         __syncthreads();
     }
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_query_overflow(GridVie
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
         const int64_t i = overflow[1 + e];
         TopK<K> top;
-        full_scan_topk<K>(g, q[i], q[nq + i], q[2 * nq + i], k, gate2, top, s_lists);
+        full_scan_topk<K>(g, 0, g.n, q[i], q[nq + i], q[2 * nq + i], k, gate2, top, s_lists);
         if (threadIdx.x == 0) store_knn<K>(top, k, i, idx, d2);
         __syncthreads();
     }
@@ -480,24 +482,23 @@ __global__ void k_map_covs(const uint32_t* __restrict__ svals, int64_t m, const 
 constexpr int kOverflowBlocks = 64;
 
 template <int K>
-hipError_t knn_cov_t(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps, float* covs,
-                     float* covs_sorted, int32_t* overflow, hipStream_t s) {
+hipError_t knn_cov_t(const GridView& g, const SegSet& S, int k, int mode, float eps, int32_t* overflow,
+                     hipStream_t s) {
     constexpr int kT = knn_threads<K>();
     const int per = kT / kGroup;
-    hipLaunchKernelGGL(k_knn_cov<K>, dim3((g.n + per - 1) / per), dim3(kT), 0, s, g, xyz, stride, k, mode, eps,
-                       covs, (int64_t)g.n, covs_sorted, overflow);
-    hipLaunchKernelGGL(k_knn_cov_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, xyz, stride, k, mode, eps,
-                       covs, (int64_t)g.n, covs_sorted, (const int32_t*)overflow);
+    hipLaunchKernelGGL(k_knn_cov<K>, dim3((g.n + per - 1) / per), dim3(kT), 0, s, g, S, k, mode, eps, overflow);
+    hipLaunchKernelGGL(k_knn_cov_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, S, k, mode, eps,
+                       (const int32_t*)overflow);
     return hipGetLastError();
 }
 
 template <int K>
-hipError_t knn_query_t(const GridView& g, const float* q, int64_t nq, int k, float gate2, float r_gate,
+hipError_t knn_query_t(const GridView& g, float h, const float* q, int64_t nq, int k, float gate2, float r_gate,
                        int32_t* idx, float* d2, int32_t* overflow, hipStream_t s) {
     constexpr int kT = knn_threads<K>();
     const int per = kT / kGroup;
-    hipLaunchKernelGGL(k_knn_query<K>, dim3((unsigned)((nq + per - 1) / per)), dim3(kT), 0, s, g, q, nq, k,
-                       gate2, r_gate, idx, d2, overflow);
+    hipLaunchKernelGGL(k_knn_query<K>, dim3((unsigned)((nq + per - 1) / per)), dim3(kT), 0, s, g, h, 1.0f / h, q, nq,
+                       k, gate2, r_gate, idx, d2, overflow);
     hipLaunchKernelGGL(k_knn_query_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, q, nq, k, gate2, idx, d2,
                        (const int32_t*)overflow);
     return hipGetLastError();
@@ -505,29 +506,30 @@ hipError_t knn_query_t(const GridView& g, const float* q, int64_t nq, int k, flo
 
 }  // namespace
 
-hipError_t launch_knn_cov(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps,
-                          float* covs, float* covs_sorted, int32_t* overflow, hipStream_t s) {
+hipError_t launch_knn_cov(const GridView& g, const SegSet& S, int k, int mode, float eps, int32_t* overflow,
+                          hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
-    if (k == 20) return knn_cov_t<20>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
-    if (k <= 8) return knn_cov_t<8>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
-    if (k <= 16) return knn_cov_t<16>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
-    if (k <= 32) return knn_cov_t<32>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
-    return knn_cov_t<64>(g, xyz, stride, k, mode, eps, covs, covs_sorted, overflow, s);
+    if (k == 20) return knn_cov_t<20>(g, S, k, mode, eps, overflow, s);
+    if (k <= 8) return knn_cov_t<8>(g, S, k, mode, eps, overflow, s);
+    if (k <= 16) return knn_cov_t<16>(g, S, k, mode, eps, overflow, s);
+    if (k <= 32) return knn_cov_t<32>(g, S, k, mode, eps, overflow, s);
+    return knn_cov_t<64>(g, S, k, mode, eps, overflow, s);
 }
 
-hipError_t launch_knn_query(const GridView& g, const float* q, int64_t nq, int k, float r_max, int32_t* idx,
-                            float* d2, int32_t* overflow, hipStream_t s) {
+hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q, int64_t nq, int k, float r_max,
+                            int32_t* idx, float* d2, int32_t* overflow, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     float gate2 = FLT_MAX, r_gate = FLT_MAX;
     if (r_max > 0.f) {
         gate2 = r_max * r_max;
         r_gate = r_max * 1.000001f + 1e-6f;
     }
-    if (k == 20) return knn_query_t<20>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
-    if (k <= 8) return knn_query_t<8>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
-    if (k <= 16) return knn_query_t<16>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
-    if (k <= 32) return knn_query_t<32>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
-    return knn_query_t<64>(g, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    const float h = cloud.h;
+    if (k == 20) return knn_query_t<20>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    if (k <= 8) return knn_query_t<8>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    if (k <= 16) return knn_query_t<16>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    if (k <= 32) return knn_query_t<32>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
+    return knn_query_t<64>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
 }
 
 hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s) {

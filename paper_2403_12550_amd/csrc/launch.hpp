@@ -9,20 +9,56 @@
 namespace gicp {
 
 // Scratch the radix sort needs for n keys (bytes), and the launcher.  Sorts
-// 24-bit keys with their values stably, ping-ponging between the a and b
-// buffers; *keys_out / *vals_out receive the buffers that hold the result.
+// keys of 8 * passes bits with their values stably, ping-ponging between the
+// a and b buffers; *keys_out / *vals_out receive the buffers with the result.
 size_t radix_scratch_bytes(int64_t n);
 hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
-                      void* scratch, hipStream_t s, uint32_t** keys_out, uint32_t** vals_out);
+                      int passes, void* scratch, hipStream_t s, uint32_t** keys_out, uint32_t** vals_out);
 
-// Grid over n points (SoA [3][stride]): keys + identity values.
-hipError_t launch_cell_keys(const float* xyz, int64_t n, int64_t stride, float inv_h,
-                            uint32_t* keys, uint32_t* vals, int* err, hipStream_t s);
+// One cloud of a (possibly segmented) grid.  Several clouds share one sort
+// and one cell table: the cloud index occupies the top 8 bits of the cell
+// key, so each cloud's points form the contiguous grid-order range
+// [off, off + n) and cells of different clouds never mix.
+struct Seg {
+    const float* xyz;     // SoA [3][n]
+    float* covs;          // SoA [6][n] covariance output in the cloud's order (k-NN covariance only)
+    float* covs_sorted;   // nullable: SoA [6][n] covariance output in grid order
+    int64_t off;          // first index of the cloud in the concatenation and in grid order
+    int64_t n;
+    float h, inv_h;       // the cloud's cell size
+};
+
+struct SegSet {
+    Seg one;              // the cloud when count == 1
+    const Seg* many;      // device array of `count` clouds when count > 1
+    int count;
+
+    __device__ __forceinline__ Seg get(int p) const { return count == 1 ? one : many[p]; }
+    // cloud holding concatenated (or grid-order) index i
+    __device__ __forceinline__ int find(int64_t i) const {
+        if (count == 1) return 0;
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (many[mid].off <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+};
+
+constexpr int kMaxSegments = 256;
+
+// Cell keys of the concatenated clouds (cloud index << 24 | cell key) with
+// their concatenated indices as values.
+hipError_t launch_cell_keys(const SegSet& S, int64_t total, uint32_t* keys, uint32_t* vals, int* err,
+                            hipStream_t s);
 // Fill the hash table with empty entries.
 hipError_t launch_table_clear(uint4* table, uint32_t cap, hipStream_t s);
-// Gather points into cell order (float4 x,y,z,orig) and insert cell runs.
-hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int64_t n, const float* xyz,
-                              int64_t stride, float4* spts, uint4* table, uint32_t mask, hipStream_t s);
+// Gather points into cell order (float4 x, y, z, index within the cloud) and
+// insert the cell runs.
+hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int64_t total, const SegSet& S,
+                              float4* spts, uint4* table, uint32_t mask, hipStream_t s);
 
 // A built grid: cell-sorted points and the cell table.
 struct GridView {
@@ -33,14 +69,15 @@ struct GridView {
     float h, inv_h;
 };
 
-// Fused self k-NN + covariance + regularisation; covs SoA [6][n] in original order.
-// covs_sorted (nullable) additionally receives the covariances in grid order.
-// overflow: device int32 [1 + n], overflow[0] zeroed by the caller (queries
-// whose grid search could not be proven exact are finished by a second pass).
-hipError_t launch_knn_cov(const GridView& g, const float* xyz, int64_t stride, int k, int mode, float eps,
-                          float* covs, float* covs_sorted, int32_t* overflow, hipStream_t s);
-// k-NN of arbitrary queries (SoA [3][nq]); idx/d2 row-major [nq][k]; overflow [1 + nq].
-hipError_t launch_knn_query(const GridView& g, const float* q, int64_t nq, int k, float r_max,
+// Fused self k-NN + covariance + regularisation of every cloud of the grid;
+// each cloud's Seg names its outputs.  overflow: device int32 [1 + total],
+// overflow[0] zeroed by the caller (queries whose grid search could not be
+// proven exact are finished by a second pass).
+hipError_t launch_knn_cov(const GridView& g, const SegSet& S, int k, int mode, float eps, int32_t* overflow,
+                          hipStream_t s);
+// k-NN of arbitrary queries (SoA [3][nq]) in a one-cloud grid; idx/d2
+// row-major [nq][k]; overflow [1 + nq].
+hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q, int64_t nq, int k, float r_max,
                             int32_t* idx, float* d2, int32_t* overflow, hipStream_t s);
 // k-th neighbour distance of `ns` evenly strided samples by brute force.
 hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s);
