@@ -116,6 +116,19 @@ def time_frames(ctx, gmap, frames, seq, prm, order, batch, prof=False):
     return time.perf_counter() - t0, poses, iters, statuses
 
 
+def copy_calibration(mib):
+    """A plain copy of `mib` MiB: under a counter profiler its FETCH_SIZE and
+    WRITE_SIZE per dispatch give the counter's reading for a known byte count."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.arange(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {mib} MiB five times")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,7 +141,13 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=4, help="frames the CPU oracle baseline registers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--c4", action="store_true", help="also time the 64-problem batch workload")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
+                         "the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a batch of registrations "

@@ -238,6 +238,74 @@ enum { GICP_PROF_LINEARIZE = 0, GICP_PROF_KNN_COV = 1, GICP_PROF_GRID = 2, GICP_
 int gicp_profile(gicp_ctx* ctx, int enable);
 int gicp_profile_read(gicp_ctx* ctx, int group, int64_t* launches, double* total_ms, double* units);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (an extension: the paper starts every registration from
+ * the previous pose).  A PointNet-style regressor maps a frame pair to its
+ * relative pose, used as the initial pose of the registration; callers fall
+ * back to the constant-velocity prediction when it fails.  Per pair, N =
+ * GICP_MLP_POINTS rows X_r = [(s_r - c) * SCALE ; (t_r - c) * SCALE] (a chosen
+ * source point, a chosen target point, c = mean of the chosen target points):
+ *     H1 = relu(X W1 + b1) 6->64, H2 = relu(H1 W2 + b2) 64->128,
+ *     H3 = relu(H2 W3 + b3) 128->256, g = max over rows of H3 (lowest row on
+ *     ties), z = relu(g W4 + b4) 256->128, y = z W5 + b5 128->6.
+ * y = [rotation vector ; translation (m)] of the relative pose in the centred
+ * frame; in the original frame T = [R, t' - (R - I) c], R = exp([y0..2]x).
+ * Loss: (1/B) sum_b 1/2 |y_b - y*_b|^2.  Adam (beta 0.9 / 0.999, eps 1e-8).
+ * Precision: X, W1..W3 and H1, H2 stored as bf16; W2, W3 products on the
+ * matrix cores with FP32 accumulation; everything else FP32.
+ *
+ * Buffers (device, caller-owned):
+ *   params  float[GICP_MLP_PARAMS]  W1[6][64] b1[64] W2[64][128] b2[128]
+ *           W3[128][256] b3[256] W4[256][128] b4[128] W5[128][6] b5[6]
+ *   m, v    float[GICP_MLP_PARAMS]  Adam moments
+ *   wbf16   uint16[GICP_MLP_BF16]   bf16 copies of W2, W3 in matrix-core
+ *           fragment order, kept in step with params by the calls below
+ *   X       uint16 (bf16 bits)[B][GICP_MLP_POINTS][6]
+ *   cache   float[B][GICP_MLP_CACHE] forward values the backward pass needs
+ * ------------------------------------------------------------------------ */
+#define GICP_MLP_POINTS 4096
+#define GICP_MLP_PARAMS 75462
+#define GICP_MLP_BF16 40960
+#define GICP_MLP_CACHE 640
+#define GICP_MLP_SCALE 0.5
+#define GICP_MLP_MAX_BATCH 4096
+
+/* One pair for gicp_mlp_pack: device pointers; src_idx / tgt_idx hold
+ * GICP_MLP_POINTS indices into the clouds (out-of-range indices are read as
+ * 0 and reported as GICP_E_ARG by the next synchronising call). */
+typedef struct gicp_mlp_pair {
+    const float* src;        /* SoA [3][n_src] */
+    int64_t n_src;
+    const float* tgt;        /* SoA [3][n_tgt] */
+    int64_t n_tgt;
+    const int32_t* src_idx;  /* [GICP_MLP_POINTS] */
+    const int32_t* tgt_idx;  /* [GICP_MLP_POINTS] */
+} gicp_mlp_pair;
+
+/* Draws the parameters: weight j of the flat vector is a (2u - 1) with
+ * a = sqrt(6 / fan_in) and u = (SplitMix64(seed * 2^32 + j) >> 11) * 2^-53
+ * (SplitMix64: Steele, Lea & Flood 2014); biases 0; m and v (nullable) 0;
+ * fills wbf16. */
+int gicp_mlp_init(gicp_ctx* ctx, uint64_t seed, float* params, float* m, float* v, uint16_t* wbf16, void* stream);
+/* Refreshes wbf16 from params (after the caller changed params). */
+int gicp_mlp_sync_weights(gicp_ctx* ctx, const float* params, uint16_t* wbf16, void* stream);
+/* Packs B pairs (host array of descriptors, 1 <= B <= GICP_MLP_MAX_BATCH)
+ * into X; centres (device double[B][3], nullable) receives c. */
+int gicp_mlp_pack(gicp_ctx* ctx, int B, const gicp_mlp_pair* pairs, uint16_t* X, double* centres, void* stream);
+/* Forward pass of B pairs: y (device float[B][6], nullable), cache (nullable;
+ * required for gicp_mlp_backward), poses (device double[B][16], nullable:
+ * the decoded relative poses, needs centres). */
+int gicp_mlp_forward(gicp_ctx* ctx, int B, const uint16_t* X, const float* params, const uint16_t* wbf16,
+                     const double* centres, float* y, float* cache, double* poses, void* stream);
+/* Gradient of the loss against targets ystar (device float[B][6]) into grad
+ * (device float[GICP_MLP_PARAMS], overwritten) and the loss (device float[1],
+ * nullable).  Deterministic: per-pair gradients are summed in pair order. */
+int gicp_mlp_backward(gicp_ctx* ctx, int B, const uint16_t* X, const float* params, const float* cache,
+                      const float* y, const float* ystar, float* grad, float* loss, void* stream);
+/* One Adam step (t = 1, 2, ...) with learning rate lr; refreshes wbf16. */
+int gicp_mlp_adam_step(gicp_ctx* ctx, float* params, float* m, float* v, const float* grad, int t, float lr,
+                       uint16_t* wbf16, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

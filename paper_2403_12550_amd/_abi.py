@@ -54,6 +54,19 @@ class Stats(C.Structure):
     ]
 
 
+class MlpPair(C.Structure):
+    _fields_ = [
+        ("src", C.c_void_p),
+        ("n_src", C.c_int64),
+        ("tgt", C.c_void_p),
+        ("n_tgt", C.c_int64),
+        ("src_idx", C.c_void_p),
+        ("tgt_idx", C.c_void_p),
+    ]
+
+
+MLP_POINTS, MLP_PARAMS, MLP_BF16, MLP_CACHE, MLP_SCALE, MLP_MAX_BATCH = 4096, 75462, 40960, 640, 0.5, 4096
+
 P = C.c_void_p
 I64 = C.c_int64
 D16 = C.c_double * 16
@@ -81,6 +94,12 @@ SIGNATURES = {
                                       C.POINTER(Stats), P]),
     "gicp_profile": (C.c_int, [P, C.c_int]),
     "gicp_profile_read": (C.c_int, [P, C.c_int, C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gicp_mlp_init": (C.c_int, [P, C.c_uint64, P, P, P, P, P]),
+    "gicp_mlp_sync_weights": (C.c_int, [P, P, P, P]),
+    "gicp_mlp_pack": (C.c_int, [P, C.c_int, C.POINTER(MlpPair), P, P, P]),
+    "gicp_mlp_forward": (C.c_int, [P, C.c_int, P, P, P, P, P, P, P, P]),
+    "gicp_mlp_backward": (C.c_int, [P, C.c_int, P, P, P, P, P, P, P, P]),
+    "gicp_mlp_adam_step": (C.c_int, [P, P, P, P, P, C.c_int, C.c_float, P, P]),
 }
 
 PROF_LINEARIZE, PROF_KNN_COV, PROF_GRID, PROF_SOLVE = 0, 1, 2, 3

@@ -82,8 +82,14 @@ struct gicp_ctx {
     Buf items, arrive, chunk_prob;
     int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
+    int h_kth_cap = 0;   // clouds the pinned estimate buffer holds
     Seg* h_segs = nullptr;           // pinned [kMaxSegments]
     Buf segs;
+    // warm-start network workspaces
+    gicp_mlp_pair* h_pairs = nullptr;   // pinned [GICP_MLP_MAX_BATCH] staging of pair descriptors
+    hipEvent_t pairs_ev = nullptr;      // recorded after the last upload of h_pairs
+    bool pairs_pending = false;
+    Buf mlp_pairs, mlp_pmax, mlp_parg, mlp_gpair, mlp_lpair;
     double queue_units = 0.0;        // source points x iterations of the last queue launch
     std::vector<double> iter_units;  // per iteration: source points of the problems still running
     // kernel timing
@@ -208,16 +214,48 @@ SegSet one_cloud(const float* xyz, int64_t n, float h, float* covs = nullptr, fl
     return S;
 }
 
-float estimate_cell(gicp_ctx* ctx, const float* xyz, int64_t n, int k, hipStream_t s) {
-    const int ns = (int)std::min<int64_t>(256, n);
-    float* d = ensure<float>(ctx->kth, ns);
-    check(launch_kth_distance(xyz, n, std::min<int>(k, (int)n), ns, d, s));
-    check(hipMemcpyAsync(ctx->h_kth, d, ns * sizeof(float), hipMemcpyDeviceToHost, s));
+// Grid cell size for a k-NN search: 1.1 x the 75th percentile of the k-th
+// neighbour distance of 256 strided sample points.  Above kEstimateScan
+// points the distances are taken among every step-th point only, at the
+// neighbour rank that covers the same area on a surface (rank k / step), so
+// the estimate costs a fixed amount of work.  All clouds are estimated
+// behind one synchronisation.
+constexpr int kEstimateSamples = 256;
+constexpr int64_t kEstimateScan = 16384;
+
+void estimate_cells(gicp_ctx* ctx, int count, const float* const* xyz, const int64_t* n, int k, hipStream_t s,
+                    float* cells) {
+    if (count <= 0) return;
+    float* d = ensure<float>(ctx->kth, (int64_t)count * kEstimateSamples);
+    if (ctx->h_kth_cap < count) {
+        if (ctx->h_kth) check(hipHostFree(ctx->h_kth));
+        ctx->h_kth = nullptr;
+        ctx->h_kth_cap = 0;
+        check(hipHostMalloc(&ctx->h_kth, (size_t)count * kEstimateSamples * sizeof(float)));
+        ctx->h_kth_cap = count;
+    }
+    std::vector<int> ns(count);
+    for (int i = 0; i < count; ++i) {
+        ns[i] = (int)std::min<int64_t>(kEstimateSamples, n[i]);
+        const int64_t step = std::max<int64_t>(1, n[i] / kEstimateScan);
+        const int j = std::max(1, (int)std::lround((double)std::min<int64_t>(k, n[i]) / (double)step));
+        check(launch_kth_distance(xyz[i], n[i], j, ns[i], step, d + (int64_t)i * kEstimateSamples, s));
+    }
+    check(hipMemcpyAsync(ctx->h_kth, d, (size_t)count * kEstimateSamples * sizeof(float), hipMemcpyDeviceToHost, s));
     check(hipStreamSynchronize(s));
-    std::vector<float> v(ctx->h_kth, ctx->h_kth + ns);
-    std::sort(v.begin(), v.end());
-    float c = v[(size_t)(0.75 * (ns - 1))] * 1.1f;
-    if (!(c > 1e-6f) || !std::isfinite(c)) c = 1e-3f;
+    for (int i = 0; i < count; ++i) {
+        std::vector<float> v(ctx->h_kth + (int64_t)i * kEstimateSamples,
+                             ctx->h_kth + (int64_t)i * kEstimateSamples + ns[i]);
+        std::sort(v.begin(), v.end());
+        float c = v[(size_t)(0.75 * (ns[i] - 1))] * 1.1f;
+        if (!(c > 1e-6f) || !std::isfinite(c)) c = 1e-3f;
+        cells[i] = c;
+    }
+}
+
+float estimate_cell(gicp_ctx* ctx, const float* xyz, int64_t n, int k, hipStream_t s) {
+    float c = 0.f;
+    estimate_cells(ctx, 1, &xyz, &n, k, s, &c);
     return c;
 }
 
@@ -289,7 +327,8 @@ int gicp_create(gicp_ctx** out, int device) {
         check(hipMemset(c->d_err, 0, 256));
         check(hipMalloc(&c->d_queue, sizeof(QueueDev)));
         check(hipHostMalloc(&c->h_err, 256));
-        check(hipHostMalloc(&c->h_kth, 256 * sizeof(float)));
+        check(hipHostMalloc(&c->h_kth, kEstimateSamples * sizeof(float)));
+        c->h_kth_cap = 1;
         check(hipHostMalloc(&c->h_segs, kMaxSegments * sizeof(Seg)));
         *out = c;
         return GICP_OK;
@@ -305,8 +344,11 @@ int gicp_destroy(gicp_ctx* c) {
     (void)hipDeviceSynchronize();
     for (Buf* b : {&c->grid.keys_a, &c->grid.vals_a, &c->grid.keys_b, &c->grid.vals_b, &c->grid.scratch,
                    &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
-                   &c->nn_prev, &c->overflow})
+                   &c->nn_prev, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
+                   &c->mlp_lpair})
         release(*b);
+    if (c->h_pairs) (void)hipHostFree(c->h_pairs);
+    if (c->pairs_ev) (void)hipEventDestroy(c->pairs_ev);
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->d_state) (void)hipFree(c->d_state);
     if (c->h_state) (void)hipHostFree(c->h_state);
@@ -338,6 +380,7 @@ int gicp_sync_status(gicp_ctx* c, void* stream) {
         check(hipStreamSynchronize(s));
         if (e & kErrNonFinite) return GICP_E_NONFINITE;
         if (e & kErrInexact) return GICP_E_INEXACT;
+        if (e & kErrIndex) return GICP_E_ARG;
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);
@@ -385,9 +428,10 @@ int gicp_covariances(gicp_ctx* c, const float* pts, int64_t n, int k, float cell
         const SegSet S = one_cloud(pts, n, h, covs);
         GridView g = build_grid(c, c->grid, S, n, s);
         const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)n, -1, s);
-        int32_t* ovf = ensure<int32_t>(c->overflow, n + 1);
-        check(launch_fill_i32(ovf, 1, 0, s));
-        check(launch_knn_cov(g, S, k, reg_mode, eps, ovf, s));
+        int32_t* work = ensure<int32_t>(c->overflow, knn_cov_work_ints(n));
+        float* raw = ensure<float>(c->sscov, 6 * n);
+        check(launch_fill_i32(work, 2, 0, s));
+        check(launch_knn_cov(g, S, k, reg_mode, eps, raw, work, s));
         prof_close(c, pm, s);
         return GICP_OK;
     } catch (const HipError& e) {
@@ -498,7 +542,7 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     }
     if (nmax > 0) {
         reserve_grid(c->grid, nmax);
-        ensure<int32_t>(c->overflow, nmax + 1);
+        ensure<int32_t>(c->overflow, knn_cov_work_ints(nmax));
     }
     std::vector<const float*> scov(nprob);
     std::vector<const float4*> ssrc(nprob, nullptr);
@@ -517,6 +561,19 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     std::vector<int> todo;
     for (int p = 0; p < nprob; ++p)
         if (!probs[p].src_covs) todo.push_back(p);
+    // cell sizes of all sources at once (one synchronisation)
+    std::vector<float> cells(nprob, prm->cell_src);
+    if (prm->cell_src <= 0.f && !todo.empty()) {
+        std::vector<const float*> xs;
+        std::vector<int64_t> ns;
+        for (int p : todo) {
+            xs.push_back(probs[p].src);
+            ns.push_back(probs[p].n);
+        }
+        std::vector<float> est(todo.size());
+        estimate_cells(c, (int)todo.size(), xs.data(), ns.data(), prm->k, s, est.data());
+        for (size_t q = 0; q < todo.size(); ++q) cells[todo[q]] = est[q];
+    }
     for (size_t g0 = 0; g0 < todo.size(); g0 += kMaxSegments) {
         const size_t g1 = std::min(todo.size(), g0 + kMaxSegments);
         const int cnt = (int)(g1 - g0);
@@ -530,7 +587,7 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
                 dst = wcov;
                 wcov += 6 * P.n;
             }
-            const float h = prm->cell_src > 0.f ? prm->cell_src : estimate_cell(c, P.src, P.n, prm->k, s);
+            const float h = cells[p];
             Seg& sg = c->h_segs[q - g0];
             sg.xyz = P.src;
             sg.covs = dst;
@@ -555,9 +612,9 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         }
         GridView g = build_grid(c, c->grid, S, total, s, wsrc);
         const int pm = prof_open(c, GICP_PROF_KNN_COV, (double)total, -1, s);
-        int32_t* ovf = static_cast<int32_t*>(c->overflow.p);
-        check(launch_fill_i32(ovf, 1, 0, s));
-        check(launch_knn_cov(g, S, prm->k, prm->reg_mode, prm->eps, ovf, s));
+        int32_t* work = static_cast<int32_t*>(c->overflow.p);
+        check(launch_fill_i32(work, 2, 0, s));
+        check(launch_knn_cov(g, S, prm->k, prm->reg_mode, prm->eps, wscov, work, s));
         prof_close(c, pm, s);
         wsrc += total;
         wscov += 6 * total;
@@ -799,3 +856,99 @@ int gicp_profile_read(gicp_ctx* c, int group, int64_t* launches, double* total_m
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// warm-start network
+// ---------------------------------------------------------------------------
+namespace {
+bool valid_batch(int B) { return B >= 1 && B <= GICP_MLP_MAX_BATCH; }
+}  // namespace
+
+int gicp_mlp_init(gicp_ctx* c, uint64_t seed, float* params, float* m, float* v, uint16_t* wbf16, void* stream) {
+    if (!c || !params || !wbf16 || seed >= (1ull << 32)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        check(launch_mlp_init(seed, params, m, v, wbf16, (hipStream_t)stream));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_mlp_sync_weights(gicp_ctx* c, const float* params, uint16_t* wbf16, void* stream) {
+    if (!c || !params || !wbf16) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        check(launch_mlp_fragments(params, wbf16, (hipStream_t)stream));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_mlp_pack(gicp_ctx* c, int B, const gicp_mlp_pair* pairs, uint16_t* X, double* centres, void* stream) {
+    if (!c || !pairs || !X || !valid_batch(B)) return GICP_E_ARG;
+    for (int i = 0; i < B; ++i) {
+        const gicp_mlp_pair& P = pairs[i];
+        if (!P.src || !P.tgt || !P.src_idx || !P.tgt_idx || P.n_src < 1 || P.n_tgt < 1) return GICP_E_ARG;
+    }
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        if (!c->h_pairs) {
+            check(hipHostMalloc(&c->h_pairs, GICP_MLP_MAX_BATCH * sizeof(gicp_mlp_pair)));
+            check(hipEventCreateWithFlags(&c->pairs_ev, hipEventDisableTiming));
+        }
+        if (c->pairs_pending) check(hipEventSynchronize(c->pairs_ev));   // the staging copy is reused
+        std::memcpy(c->h_pairs, pairs, B * sizeof(gicp_mlp_pair));
+        gicp_mlp_pair* dp = ensure<gicp_mlp_pair>(c->mlp_pairs, GICP_MLP_MAX_BATCH);
+        check(hipMemcpyAsync(dp, c->h_pairs, B * sizeof(gicp_mlp_pair), hipMemcpyHostToDevice, s));
+        check(hipEventRecord(c->pairs_ev, s));
+        c->pairs_pending = true;
+        check(launch_mlp_pack(B, dp, X, centres, c->d_err, s));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_mlp_forward(gicp_ctx* c, int B, const uint16_t* X, const float* params, const uint16_t* wbf16,
+                     const double* centres, float* y, float* cache, double* poses, void* stream) {
+    if (!c || !X || !params || !wbf16 || !valid_batch(B) || (poses && !centres)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        const size_t np = (size_t)B * mlp_splits() * 256;
+        float* pmax = ensure<float>(c->mlp_pmax, np);
+        int* parg = ensure<int>(c->mlp_parg, np);
+        check(launch_mlp_forward(B, X, params, wbf16, pmax, parg, centres, y, cache, poses, (hipStream_t)stream));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_mlp_backward(gicp_ctx* c, int B, const uint16_t* X, const float* params, const float* cache,
+                      const float* y, const float* ystar, float* grad, float* loss, void* stream) {
+    if (!c || !X || !params || !cache || !y || !ystar || !grad || !valid_batch(B)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        float* gpair = ensure<float>(c->mlp_gpair, (size_t)B * GICP_MLP_PARAMS);
+        float* lpair = ensure<float>(c->mlp_lpair, (size_t)B);
+        check(launch_mlp_backward(B, X, params, cache, y, ystar, gpair, lpair, grad, loss, (hipStream_t)stream));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_mlp_adam_step(gicp_ctx* c, float* params, float* m, float* v, const float* grad, int t, float lr,
+                       uint16_t* wbf16, void* stream) {
+    if (!c || !params || !m || !v || !grad || !wbf16 || t < 1 || !(lr > 0.f)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        check(launch_mlp_adam(params, m, v, grad, t, lr, wbf16, (hipStream_t)stream));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}

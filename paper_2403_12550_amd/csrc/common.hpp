@@ -19,6 +19,7 @@ constexpr int kNumAcc = 29;           // 21 unique H terms, 6 b terms, cost, inl
 // Error bits recorded on the device (context error word).
 constexpr int kErrNonFinite = 1;
 constexpr int kErrInexact = 2;
+constexpr int kErrIndex = 4;       // an index argument read on the device was out of range
 
 // ---------------------------------------------------------------------------
 // Grid cells.  A point p lies in cell floor(p * inv_h) per axis; the cell key

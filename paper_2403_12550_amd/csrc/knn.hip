@@ -2,14 +2,16 @@
 // covariance and its scale regularisation (Sec. 3: covariance of the k nearest
 // neighbours; Sec. 3.1: C = R Lambda^2 R^T, plane and ellipse forms).
 //
-// One lane per query.  Queries of the self k-NN are the cell-sorted points
-// themselves, so neighbouring lanes visit the same cells and the candidate
-// reads are served by the vector L1/L2.  Each lane keeps its k best
-// candidates in registers as 64-bit (FP32 key, original index) words, sorted,
-// and inserts with an unrolled compare-exchange chain.  After the 27-cell
-// block the lane proves exactness (the k-th key is below the squared
-// clearance of the scanned block); otherwise it scans the next shell of cells,
-// and after kMaxShell shells the whole cloud.
+// A group of four consecutive lanes serves one query: the lanes split the
+// cells of the 27-cell block, each keeps its own best candidates in registers
+// as 64-bit (FP32 key, original index) words, sorted, inserted with an
+// unrolled compare-exchange chain, and the four lists are merged through LDS.
+// Queries of the self k-NN are the cell-sorted points themselves, so the
+// groups of a wavefront visit the same cells and the candidate reads are
+// served by the vector L1/L2.  After the 27-cell block the group proves
+// exactness (the k-th key is below the squared clearance of the scanned
+// block); otherwise it scans the next shell of cells, and after kMaxShell
+// shells the query goes to a whole-cloud scan by one workgroup.
 #include <float.h>
 
 #include "common.hpp"
@@ -65,20 +67,51 @@ __device__ __forceinline__ float prune_bound(const TopK<K>& top, float gate2) {
     return fminf(kth, gate2);
 }
 
+// Publish the lanes' sorted lists in `lists` (LDS, [kGroup][K]) and merge
+// them into every lane's `top`.  A word present in several lists (the
+// common prefix the lanes started a shell from) is taken once.
+template <int K>
+__device__ __forceinline__ void merge_lists(TopK<K>& top, int k, int l, uint64_t* lists) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) lists[l * K + j] = top.v[j];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the real entries of every list sit in [K - k, K)
+    int h0 = K - k, h1 = K - k, h2 = K - k, h3 = K - k;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j < K - k) continue;   // dummy slots keep their zero words
+        const uint64_t a0 = h0 < K ? lists[0 * K + h0] : ~0ull;
+        const uint64_t a1 = h1 < K ? lists[1 * K + h1] : ~0ull;
+        const uint64_t a2 = h2 < K ? lists[2 * K + h2] : ~0ull;
+        const uint64_t a3 = h3 < K ? lists[3 * K + h3] : ~0ull;
+        const uint64_t m01 = a0 < a1 ? a0 : a1;
+        const uint64_t m23 = a2 < a3 ? a2 : a3;
+        const uint64_t m = m01 < m23 ? m01 : m23;
+        top.v[j] = m;
+        h0 += (m == a0) ? 1 : 0;
+        h1 += (m == a1) ? 1 : 0;
+        h2 += (m == a2) ? 1 : 0;
+        h3 += (m == a3) ? 1 : 0;
+    }
+    // the next publication overwrites the lists: every lane has read them
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Exact k-NN of q by a group of kGroup consecutive lanes (lane l; all hold
 // q).  Each lane fills its own top-k from every kGroup-th cell of the 27-cell
 // block (nearest cells first; a cell is skipped when its distance lower bound
-// exceeds the lane's current k-th key or the gate).  The lanes publish their
-// sorted lists in `lists` (LDS, [kGroup][K]) and every lane merges the four
-// lists into the group's top-k, so the group continues converged.  Exactness
-// is then proven from the block clearance; the rare remaining cases scan the
-// next shells on the merged list, redundantly on the group's lanes.  Returns
-// false when kMaxShell shells did not prove the result exact: the caller then
-// hands the query to the overflow pass (a full scan by a whole workgroup).
+// exceeds the lane's current k-th key or the gate), and the four lists are
+// merged, so the group continues converged.  Exactness is then proven from
+// the block clearance; otherwise the lanes split the cells of the next shell
+// the same way, starting from the merged list, and merge again.  Returns
+// false when max_shell shells did not prove the result exact: the caller then
+// hands the query on (to a later pass or to a whole-cloud scan).
 template <int K>
 __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv_h, uint32_t prefix, float qx,
                                            float qy, float qz, int k, float gate2, float r_gate, TopK<K>& top, int l,
-                                           uint64_t* lists) {
+                                           uint64_t* lists, int max_shell = kMaxShell) {
     top.init(k);
     const bool fin = finite3(qx, qy, qz);   // a non-finite query has no neighbour with a finite distance
     const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, inv_h);
@@ -92,29 +125,7 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
             scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
         }
     }
-    // publish and merge: the real entries of every list sit in [K - k, K)
-#pragma unroll
-    for (int j = 0; j < K; ++j) lists[l * K + j] = top.v[j];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int h0 = K - k, h1 = K - k, h2 = K - k, h3 = K - k;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j < K - k) continue;   // dummy slots keep their zero words
-        const uint64_t a0 = h0 < K ? lists[0 * K + h0] : ~0ull;
-        const uint64_t a1 = h1 < K ? lists[1 * K + h1] : ~0ull;
-        const uint64_t a2 = h2 < K ? lists[2 * K + h2] : ~0ull;
-        const uint64_t a3 = h3 < K ? lists[3 * K + h3] : ~0ull;
-        const uint64_t m01 = a0 < a1 ? a0 : a1;
-        const uint64_t m23 = a2 < a3 ? a2 : a3;
-        const uint64_t m = m01 < m23 ? m01 : m23;
-        top.v[j] = m;
-        if (m == a0) ++h0;
-        else if (m == a1) ++h1;
-        else if (m == a2) ++h2;
-        else ++h3;
-    }
+    merge_lists<K>(top, k, l, lists);
     if (!fin) return true;
     for (int R = 1;; ++R) {
         const float clr = block_clearance(qx, qy, qz, c, R, h);
@@ -126,16 +137,18 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
                 if (kkey < clr * clr * (1.f - 1e-6f)) return true;
             }
         }
-        if (R >= kMaxShell) return false;   // left to the overflow pass
-        const int S = R + 1;
-        for (int dz = -S; dz <= S; ++dz)
-            for (int dy = -S; dy <= S; ++dy)
-                for (int dx = -S; dx <= S; ++dx) {
-                    if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
-                    const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
-                    if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-                    scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
-                }
+        if (R >= max_shell) return false;
+        // shell S = R + 1: the cells at Chebyshev distance S, every kGroup-th
+        // one per lane (positions of the (2S+1)^3 cube, interior skipped)
+        const int S = R + 1, W = 2 * S + 1;
+        for (int t = l; t < W * W * W; t += kGroup) {
+            const int dx = t % W - S, dy = (t / W) % W - S, dz = t / (W * W) - S;
+            if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
+            const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
+            if (cell_pruned(lb, prune_bound(top, gate2))) continue;
+            scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+        }
+        merge_lists<K>(top, k, l, lists);
     }
 }
 
@@ -229,37 +242,57 @@ constexpr int knn_threads() {
     return K <= 32 ? 256 : 128;
 }
 
-// Covariance of the k neighbours in `top` (shifted by the query point q, which
-// is itself a neighbour), regularised (Sec. 3.1).
+// Covariance from the shifted moments m = (sum d, sum d d^T (xx,xy,xz,yy,yz,zz),
+// count) with the 1/k normalisation and the neighbourhood mean.
+__device__ __forceinline__ Sym3 moments_to_cov(const float m[10]) {
+    const float ik = 1.f / fmaxf(m[9], 1.f);
+    const float mx = m[0] * ik, my = m[1] * ik, mz = m[2] * ik;
+    Sym3 C;
+    C.a00 = m[3] * ik - mx * mx;
+    C.a01 = m[4] * ik - mx * my;
+    C.a02 = m[5] * ik - mx * mz;
+    C.a11 = m[6] * ik - my * my;
+    C.a12 = m[7] * ik - my * mz;
+    C.a22 = m[8] * ik - mz * mz;
+    return C;
+}
+
+// Moments of one neighbour slot, shifted by the query point.
+__device__ __forceinline__ void add_moments(float m[10], uint64_t v, const float* __restrict__ xyz, int64_t stride,
+                                            float qx, float qy, float qz) {
+    const uint32_t id = (uint32_t)(v & 0xFFFFFFFFu);
+    const float dx = xyz[id] - qx, dy = xyz[stride + id] - qy, dz = xyz[2 * stride + id] - qz;
+    m[0] += dx; m[1] += dy; m[2] += dz;
+    m[3] += dx * dx; m[4] += dx * dy; m[5] += dx * dz;
+    m[6] += dy * dy; m[7] += dy * dz; m[8] += dz * dz;
+    m[9] += 1.f;
+}
+
+// Raw covariance of the k neighbours in `top` (moments shifted by the query
+// point q, which is itself a neighbour), by one thread, in the summation
+// order of the lane-group version below (four strided partial sums combined
+// as (s0 + s1) + (s2 + s3)), so that a point gets the same bits whichever
+// pass finds its neighbours.
 template <int K>
-__device__ __forceinline__ void cov_from_topk(const TopK<K>& top, int k, const float* __restrict__ xyz,
-                                              int64_t stride, float qx, float qy, float qz, int mode, float eps,
-                                              float out[6]) {
-    float s1x = 0, s1y = 0, s1z = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
-    int found = 0;
+__device__ __forceinline__ Sym3 raw_from_topk(const TopK<K>& top, int k, const float* __restrict__ xyz,
+                                              int64_t stride, float qx, float qy, float qz) {
+    float part[kGroup][10];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        // a slot stays empty only when fewer than k neighbours have a finite
-        // distance (non-finite input, reported through the error word)
-        if (j >= K - k && top.v[j] != ~0ull) {
-            const uint32_t id = (uint32_t)(top.v[j] & 0xFFFFFFFFu);
-            const float dx = xyz[id] - qx, dy = xyz[stride + id] - qy, dz = xyz[2 * stride + id] - qz;
-            s1x += dx; s1y += dy; s1z += dz;
-            sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
-            syy += dy * dy; syz += dy * dz; szz += dz * dz;
-            ++found;
+    for (int l = 0; l < kGroup; ++l) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) part[l][c] = 0.f;
+#pragma unroll
+        for (int jj = 0; jj < K / kGroup; ++jj) {
+            const int j = kGroup * jj + l;
+            // a slot stays empty only when fewer than k neighbours have a
+            // finite distance (non-finite input, reported through the error word)
+            if (j >= K - k && top.v[j] != ~0ull) add_moments(part[l], top.v[j], xyz, stride, qx, qy, qz);
         }
     }
-    const float ik = 1.f / (float)max(found, 1);
-    const float mx = s1x * ik, my = s1y * ik, mz = s1z * ik;
-    Sym3 C;
-    C.a00 = sxx * ik - mx * mx;
-    C.a01 = sxy * ik - mx * my;
-    C.a02 = sxz * ik - mx * mz;
-    C.a11 = syy * ik - my * my;
-    C.a12 = syz * ik - my * mz;
-    C.a22 = szz * ik - mz * mz;
-    regularise(C, mode, eps, out);
+    float m[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) m[c] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
+    return moments_to_cov(m);
 }
 
 __device__ __forceinline__ void store_cov(const float out[6], float* __restrict__ covs, float* __restrict__ covs_sorted,
@@ -272,26 +305,137 @@ __device__ __forceinline__ void store_cov(const float out[6], float* __restrict_
     }
 }
 
+// Slot 4*jj + l of the (group-uniform) sorted list, picked without dynamic
+// register indexing.
 template <int K>
-__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, SegSet S, int k, int mode, float eps,
-                                                              int32_t* __restrict__ overflow) {
+__device__ __forceinline__ uint64_t lane_slot(const TopK<K>& top, int jj, int l) {
+    const uint64_t a = top.v[4 * jj], b = top.v[4 * jj + 1], c = top.v[4 * jj + 2], d = top.v[4 * jj + 3];
+    return l == 0 ? a : l == 1 ? b : l == 2 ? c : d;
+}
+
+// Raw covariance of the group's (uniform) top-k: every lane sums the moments
+// of a quarter of the slots, and the four partial sums are combined across
+// the group's lanes.
+template <int K>
+__device__ __forceinline__ Sym3 raw_from_topk_group(const TopK<K>& top, int k, int l, const float* __restrict__ xyz,
+                                                    int64_t stride, float qx, float qy, float qz) {
+    static_assert(K % kGroup == 0, "list length must split over the group lanes");
+    float m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int jj = 0; jj < K / kGroup; ++jj) {
+        const uint64_t v = lane_slot<K>(top, jj, l);
+        if (kGroup * jj + l >= K - k && v != ~0ull) add_moments(m, v, xyz, stride, qx, qy, qz);
+    }
+    // lane l holds s_l; after the two exchanges every lane holds
+    // (s0 + s1) + (s2 + s3) (additions commute bit for bit)
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+        m[c] += __shfl_xor(m[c], 1);
+        m[c] += __shfl_xor(m[c], 2);
+    }
+    return moments_to_cov(m);
+}
+
+// Raw covariances go to `raw`, laid out per cloud as SoA [6][n] at 6 * off
+// (cell order); the regularisation pass turns them into the outputs.
+__device__ __forceinline__ void store_raw(const Sym3& C, float* __restrict__ raw, const Seg& sg, int64_t s) {
+    float* r = raw + 6 * sg.off + (s - sg.off);
+    r[0] = C.a00;
+    r[sg.n] = C.a01;
+    r[2 * sg.n] = C.a02;
+    r[3 * sg.n] = C.a11;
+    r[4 * sg.n] = C.a12;
+    r[5 * sg.n] = C.a22;
+}
+
+// Work lists of the self k-NN: [0] retry count, [1] overflow count, then the
+// retry list (n entries) and the overflow list (n entries).
+__device__ __forceinline__ void push_work(int32_t* work, int64_t n, int which, int64_t s) {
+    int32_t* list = work + 2 + which * n;
+    list[atomicAdd(&work[which], 1)] = (int32_t)s;
+}
+
+// Gate of the first pass, as a multiple of the cell size: the cell is about
+// 1.1 times the typical k-th neighbour distance, so most points find their k
+// neighbours inside it.
+constexpr float kGateCells = 1.25f;
+
+// Self k-NN + raw covariance, first pass.  A group of kGroup lanes serves one
+// cell-sorted point.  Only candidates inside a key gate of (kGateCells h)^2
+// enter the lists, which removes most insertions; the result is exact whenever
+// the list fills up (every point ranked before the k-th then lies inside the
+// gate and was seen).  Points whose list does not fill, or whose search did
+// not finish, go to the retry list.
+template <int K>
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, SegSet S, int k, float* __restrict__ raw,
+                                                              int32_t* __restrict__ work) {
     constexpr int kT = knn_threads<K>();
     __shared__ uint64_t s_lists[kT / kGroup][kGroup * K];
     const int l = threadIdx.x & (kGroup - 1);
-    const int32_t s = blockIdx.x * (kT / kGroup) + threadIdx.x / kGroup;
+    const int64_t s = (int64_t)blockIdx.x * (kT / kGroup) + threadIdx.x / kGroup;
     if (s >= g.n) return;   // uniform over each lane group
     const int p = S.find(s);
     const Seg sg = S.get(p);
     const float4 q = g.spts[s];
+    const float gate = kGateCells * sg.h;
+    const float gate2 = gate * gate;
     TopK<K> top;
-    if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, FLT_MAX, FLT_MAX, top,
-                       l, s_lists[threadIdx.x / kGroup])) {
-        if (l == 0) overflow[1 + atomicAdd(&overflow[0], 1)] = s;
+    const bool ok = knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, gate2,
+                                  gate * 1.000001f + 1e-6f, top, l, s_lists[threadIdx.x / kGroup]);
+    if (!ok || top.v[K - 1] == ~0ull) {
+        if (l == 0) push_work(work, g.n, 0, s);
         return;
     }
+    const Sym3 C = raw_from_topk_group<K>(top, k, l, sg.xyz, sg.n, q.x, q.y, q.z);
+    if (l == 0) store_raw(C, raw, sg, s);
+}
+
+// Second pass over the retry list: the same search without a gate.  The list
+// is short, so its queries are spread one per workgroup of a small block
+// first (query e goes to block e mod gridDim.x), to use every compute unit.
+// Points it cannot prove exact within kMaxShell shells go to the overflow list.
+constexpr int kRetryThreads = 64;
+
+template <int K>
+__global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, SegSet S, int k,
+                                                                 float* __restrict__ raw,
+                                                                 int32_t* __restrict__ work) {
+    constexpr int kG = kRetryThreads / kGroup;
+    __shared__ uint64_t s_lists[kG][kGroup * K];
+    const int l = threadIdx.x & (kGroup - 1);
+    const int grp = threadIdx.x / kGroup;
+    const int count = work[0];
+    const int32_t* list = work + 2;
+    for (int64_t e = blockIdx.x + (int64_t)gridDim.x * grp; e < count; e += (int64_t)gridDim.x * kG) {
+        const int64_t s = list[e];
+        const int p = S.find(s);
+        const Seg sg = S.get(p);
+        const float4 q = g.spts[s];
+        TopK<K> top;
+        if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, FLT_MAX, FLT_MAX,
+                           top, l, s_lists[grp])) {
+            if (l == 0) push_work(work, g.n, 1, s);
+            continue;
+        }
+        const Sym3 C = raw_from_topk_group<K>(top, k, l, sg.xyz, sg.n, q.x, q.y, q.z);
+        if (l == 0) store_raw(C, raw, sg, s);
+    }
+}
+
+// Regularisation pass, one lane per point in cell order: raw covariance ->
+// scale-regularised covariance (Sec. 3.1), written in the cloud's order and,
+// when requested, in cell order.
+__global__ __launch_bounds__(kBlock) void k_cov_regularise(GridView g, SegSet S, int mode, float eps,
+                                                           const float* __restrict__ raw) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    const Seg sg = S.get(S.find(s));
+    const float* r = raw + 6 * sg.off + (s - sg.off);
+    Sym3 C;
+    C.a00 = r[0]; C.a01 = r[sg.n]; C.a02 = r[2 * sg.n]; C.a11 = r[3 * sg.n]; C.a12 = r[4 * sg.n]; C.a22 = r[5 * sg.n];
     float out[6];
-    cov_from_topk<K>(top, k, sg.xyz, sg.n, q.x, q.y, q.z, mode, eps, out);
-    if (l == 0) store_cov(out, sg.covs, sg.covs_sorted, sg.n, __float_as_uint(q.w), (int32_t)(s - sg.off));
+    regularise(C, mode, eps, out);
+    store_cov(out, sg.covs, sg.covs_sorted, sg.n, __float_as_uint(g.spts[s].w), (int32_t)(s - sg.off));
 }
 
 template <int K>
@@ -369,23 +513,20 @@ __device__ __forceinline__ void full_scan_topk(const GridView& g, int64_t lo, in
 }
 
 template <int K>
-__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov_overflow(GridView g, SegSet S, int k, int mode,
-                                                                       float eps,
-                                                                       const int32_t* __restrict__ overflow) {
+__global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov_overflow(GridView g, SegSet S, int k,
+                                                                       float* __restrict__ raw,
+                                                                       const int32_t* __restrict__ work) {
     __shared__ uint64_t s_lists[knn_threads<K>() * K];
-    const int count = overflow[0];
+    const int count = work[1];
+    const int32_t* list = work + 2 + g.n;
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
-        const int32_t s = overflow[1 + e];
+        const int64_t s = list[e];
         const int p = S.find(s);
         const Seg sg = S.get(p);
         const float4 q = g.spts[s];
         TopK<K> top;
         full_scan_topk<K>(g, sg.off, sg.off + sg.n, q.x, q.y, q.z, k, FLT_MAX, top, s_lists);
-        if (threadIdx.x == 0) {
-            float out[6];
-            cov_from_topk<K>(top, k, sg.xyz, sg.n, q.x, q.y, q.z, mode, eps, out);
-            store_cov(out, sg.covs, sg.covs_sorted, sg.n, __float_as_uint(q.w), (int32_t)(s - sg.off));
-        }
+        if (threadIdx.x == 0) store_raw(raw_from_topk<K>(top, k, sg.xyz, sg.n, q.x, q.y, q.z), raw, sg, s);
         __syncthreads();
     }
 }
@@ -407,22 +548,25 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_query_overflow(GridVie
     }
 }
 
-// Brute-force distance to the k-th neighbour of `ns` strided samples: one
-// workgroup per sample, each lane keeps its own top-k over a strided slice,
-// then lane 0 merges the slices through LDS.
-__global__ __launch_bounds__(256) void k_kth_distance(const float* __restrict__ xyz, int64_t n, int k, int ns,
-                                                      float* __restrict__ out) {
-    __shared__ float s_keys[256 * 8];
-    const int64_t qi = (int64_t)blockIdx.x * n / ns;
+// Distance to the j-th neighbour of `ns` evenly strided samples among every
+// `step`-th point of the cloud (brute force), one wavefront per sample: each
+// lane keeps its 8 smallest keys over a strided slice, then the wavefront
+// pops the smallest head j times (an upper bound of the true j-th when a lane
+// held more than 8 of the j smallest; used only to size grid cells).
+constexpr int kKthWaves = 4;
+
+__global__ __launch_bounds__(64 * kKthWaves) void k_kth_distance(const float* __restrict__ xyz, int64_t n, int j,
+                                                                 int ns, int64_t step, float* __restrict__ out) {
+    const int sample = blockIdx.x * kKthWaves + threadIdx.x / 64;
+    if (sample >= ns) return;   // uniform over the wavefront
+    const int lane = threadIdx.x % 64;
+    const int64_t qi = (int64_t)sample * n / ns;
     const float qx = xyz[qi], qy = xyz[n + qi], qz = xyz[2 * n + qi];
-    // each lane: its 8 smallest keys (k-th of the union is found by repeated
-    // selection below; k <= 64 needs at most 8 per lane only if the k smallest
-    // are spread, so lanes keep 8 and the merge is exact for k <= 8 per lane)
     float best[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) best[j] = FLT_MAX;
-    for (int64_t j = threadIdx.x; j < n; j += 256) {
-        const float d = rank_key(qx, qy, qz, xyz[j], xyz[n + j], xyz[2 * n + j]);
+    for (int t = 0; t < 8; ++t) best[t] = FLT_MAX;
+    for (int64_t i = lane * step; i < n; i += 64 * step) {
+        const float d = rank_key(qx, qy, qz, xyz[i], xyz[n + i], xyz[2 * n + i]);
         if (d < best[7]) {
             best[7] = d;
 #pragma unroll
@@ -433,31 +577,23 @@ __global__ __launch_bounds__(256) void k_kth_distance(const float* __restrict__ 
             }
         }
     }
+    int taken = 0;
+    float kth = FLT_MAX;
+    while (taken < j) {
+        float m = best[0];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s_keys[threadIdx.x * 8 + j] = best[j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // k-th smallest of the 2048 lane candidates by repeated extraction
-        // (an upper bound of the true k-th when a lane held more than 8 of the
-        // k smallest; used only to size grid cells)
-        float last = -1.f;
-        int taken = 0;
-        float kth = FLT_MAX;
-        while (taken < k) {
-            float m = FLT_MAX;
-            int cnt = 0;
-            for (int j = 0; j < 256 * 8; ++j) {
-                const float v = s_keys[j];
-                if (v > last && v < m) { m = v; cnt = 0; }
-                if (v == m) ++cnt;
-            }
-            if (m == FLT_MAX) break;
-            taken += cnt;
-            last = m;
-            kth = m;
+        for (int o = 32; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o));
+        if (m == FLT_MAX) break;
+        const bool mine = best[0] == m;
+        taken += __popcll(__ballot(mine));
+        kth = m;
+        if (mine) {
+#pragma unroll
+            for (int t = 0; t < 7; ++t) best[t] = best[t + 1];
+            best[7] = FLT_MAX;
         }
-        out[blockIdx.x] = sqrtf(kth);
     }
+    if (lane == 0) out[sample] = sqrtf(kth);
 }
 
 __global__ void k_map_covs(const uint32_t* __restrict__ svals, int64_t m, const float* __restrict__ covs,
@@ -479,16 +615,21 @@ __global__ void k_map_covs(const uint32_t* __restrict__ svals, int64_t m, const 
     scov[2 * i + 1] = make_float4(o[4], o[5], 0.f, 0.f);
 }
 
-constexpr int kOverflowBlocks = 64;
+constexpr int kOverflowBlocks = 256;
+
+constexpr int kRetryBlocks = 1024;
 
 template <int K>
-hipError_t knn_cov_t(const GridView& g, const SegSet& S, int k, int mode, float eps, int32_t* overflow,
+hipError_t knn_cov_t(const GridView& g, const SegSet& S, int k, int mode, float eps, float* raw, int32_t* work,
                      hipStream_t s) {
     constexpr int kT = knn_threads<K>();
     const int per = kT / kGroup;
-    hipLaunchKernelGGL(k_knn_cov<K>, dim3((g.n + per - 1) / per), dim3(kT), 0, s, g, S, k, mode, eps, overflow);
-    hipLaunchKernelGGL(k_knn_cov_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, S, k, mode, eps,
-                       (const int32_t*)overflow);
+    hipLaunchKernelGGL(k_knn_cov<K>, dim3((g.n + per - 1) / per), dim3(kT), 0, s, g, S, k, raw, work);
+    hipLaunchKernelGGL(k_knn_cov_retry<K>, dim3(kRetryBlocks), dim3(kRetryThreads), 0, s, g, S, k, raw, work);
+    hipLaunchKernelGGL(k_knn_cov_overflow<K>, dim3(kOverflowBlocks), dim3(kT), 0, s, g, S, k, raw,
+                       (const int32_t*)work);
+    hipLaunchKernelGGL(k_cov_regularise, dim3((g.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, S, mode, eps,
+                       (const float*)raw);
     return hipGetLastError();
 }
 
@@ -506,14 +647,14 @@ hipError_t knn_query_t(const GridView& g, float h, const float* q, int64_t nq, i
 
 }  // namespace
 
-hipError_t launch_knn_cov(const GridView& g, const SegSet& S, int k, int mode, float eps, int32_t* overflow,
+hipError_t launch_knn_cov(const GridView& g, const SegSet& S, int k, int mode, float eps, float* raw, int32_t* work,
                           hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
-    if (k == 20) return knn_cov_t<20>(g, S, k, mode, eps, overflow, s);
-    if (k <= 8) return knn_cov_t<8>(g, S, k, mode, eps, overflow, s);
-    if (k <= 16) return knn_cov_t<16>(g, S, k, mode, eps, overflow, s);
-    if (k <= 32) return knn_cov_t<32>(g, S, k, mode, eps, overflow, s);
-    return knn_cov_t<64>(g, S, k, mode, eps, overflow, s);
+    if (k == 20) return knn_cov_t<20>(g, S, k, mode, eps, raw, work, s);
+    if (k <= 8) return knn_cov_t<8>(g, S, k, mode, eps, raw, work, s);
+    if (k <= 16) return knn_cov_t<16>(g, S, k, mode, eps, raw, work, s);
+    if (k <= 32) return knn_cov_t<32>(g, S, k, mode, eps, raw, work, s);
+    return knn_cov_t<64>(g, S, k, mode, eps, raw, work, s);
 }
 
 hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q, int64_t nq, int k, float r_max,
@@ -532,8 +673,9 @@ hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q,
     return knn_query_t<64>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
 }
 
-hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_kth_distance, dim3(ns), dim3(256), 0, s, xyz, n, k, ns, out);
+hipError_t launch_kth_distance(const float* xyz, int64_t n, int j, int ns, int64_t step, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_kth_distance, dim3((ns + kKthWaves - 1) / kKthWaves), dim3(64 * kKthWaves), 0, s, xyz, n, j,
+                       ns, step, out);
     return hipGetLastError();
 }
 

@@ -69,18 +69,21 @@ struct GridView {
     float h, inv_h;
 };
 
-// Fused self k-NN + covariance + regularisation of every cloud of the grid;
-// each cloud's Seg names its outputs.  overflow: device int32 [1 + total],
-// overflow[0] zeroed by the caller (queries whose grid search could not be
-// proven exact are finished by a second pass).
-hipError_t launch_knn_cov(const GridView& g, const SegSet& S, int k, int mode, float eps, int32_t* overflow,
+// Self k-NN + covariance + regularisation of every cloud of the grid; each
+// cloud's Seg names its outputs.  raw: device float scratch [6 * total] (per
+// cloud SoA [6][n] at 6 * off; may alias the clouds' covs_sorted, which the
+// last pass rewrites in place).  work: device int32 [2 + 2 * total] with
+// work[0] = work[1] = 0 set by the caller (retry and overflow lists).
+hipError_t launch_knn_cov(const GridView& g, const SegSet& S, int k, int mode, float eps, float* raw, int32_t* work,
                           hipStream_t s);
+constexpr int64_t knn_cov_work_ints(int64_t total) { return 2 + 2 * total; }
 // k-NN of arbitrary queries (SoA [3][nq]) in a one-cloud grid; idx/d2
 // row-major [nq][k]; overflow [1 + nq].
 hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q, int64_t nq, int k, float r_max,
                             int32_t* idx, float* d2, int32_t* overflow, hipStream_t s);
-// k-th neighbour distance of `ns` evenly strided samples by brute force.
-hipError_t launch_kth_distance(const float* xyz, int64_t n, int k, int ns, float* out, hipStream_t s);
+// j-th neighbour distance of `ns` evenly strided samples among every
+// step-th point, by brute force.
+hipError_t launch_kth_distance(const float* xyz, int64_t n, int j, int ns, int64_t step, float* out, hipStream_t s);
 // Map Gaussians: regularise covariances and store them in cell order (2 x float4 each).
 hipError_t launch_map_covs(const uint32_t* svals, int64_t m, const float* covs, int64_t stride, int mode,
                            float eps, float4* scov, int* err, hipStream_t s);
@@ -147,5 +150,21 @@ hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_
 hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks, int acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
+
+// Warm-start network (mlp.hip).
+hipError_t launch_mlp_init(uint64_t seed, float* params, float* m, float* v, uint16_t* wb, hipStream_t s);
+hipError_t launch_mlp_fragments(const float* params, uint16_t* wb, hipStream_t s);
+hipError_t launch_mlp_pack(int B, const gicp_mlp_pair* pairs, uint16_t* X, double* centres, int* err,
+                           hipStream_t s);
+// pmax / parg: scratch [B][mlp_splits()][256]
+hipError_t launch_mlp_forward(int B, const uint16_t* X, const float* params, const uint16_t* wb, float* pmax,
+                              int* parg, const double* centres, float* y, float* cache, double* poses, hipStream_t s);
+// gpair: scratch [B][GICP_MLP_PARAMS]; lpair: scratch [B]
+hipError_t launch_mlp_backward(int B, const uint16_t* X, const float* params, const float* cache, const float* y,
+                               const float* ystar, float* gpair, float* lpair, float* grad, float* loss,
+                               hipStream_t s);
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int t, float lr, uint16_t* wb,
+                           hipStream_t s);
+int mlp_splits();
 
 }  // namespace gicp
