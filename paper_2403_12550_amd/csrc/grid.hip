@@ -2,15 +2,14 @@
 // (three 8-bit digit passes), and the open-addressing cell table.
 //
 // Radix sort design for wave64: each pass is (1) a per-tile digit histogram
-// (tile-major [tiles][256]), (2) one 256-thread workgroup that walks the tiles
-// (coalesced) to form every (tile, digit) scatter offset, and (3) a stable
-// scatter.  Within a tile, elements are processed in rounds of
+// (tile-major [tiles][256]), (2) one workgroup per digit that scans that
+// digit's counts over the tiles and records the digit total, and (3) a stable
+// scatter whose workgroups add the scanned digit totals to their offsets.  Within a tile, elements are processed in rounds of
 // 256 (one per lane, in order); lanes holding the same digit are found with
 // eight wavefront ballots, their rank is the popcount of the lower lanes of
 // the match mask, and per-wave digit totals in LDS order the four waves.
 // Equal digits therefore keep input order, which makes the sort stable.
-// Tiles of 1024 keys keep a 60k-point frame at ~60 workgroups and its count
-// matrix inside one scan workgroup.
+// Tiles of 1024 keys keep a 60k-point frame at ~60 workgroups.
 #include <algorithm>
 
 #include "common.hpp"
@@ -61,70 +60,63 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t* __rest
     for (int i = threadIdx.x; i < kDigits; i += kSortThreads) counts[(int64_t)blockIdx.x * kDigits + i] = s_hist[i];
 }
 
-// Scatter offsets of one pass: offsets[t][d] = (number of keys with a digit
-// below d) + (number of keys with digit d in tiles before t).  One thread per
-// digit walks the tiles in order (coalesced over the digits), then the digit
-// totals are scanned across the workgroup.
-__global__ __launch_bounds__(kDigits) void k_rs_offsets(const uint32_t* __restrict__ counts, int ntiles,
-                                                       uint32_t* __restrict__ offsets) {
-    __shared__ uint32_t s_tot[kDigits];
-    const int d = threadIdx.x;
-    uint32_t run = 0;
-    constexpr int kB = 16;   // tiles whose counts are loaded together
-    int t0 = 0;
-    for (; t0 + kB <= ntiles; t0 += kB) {
-        uint32_t c[kB];
-#pragma unroll
-        for (int r = 0; r < kB; ++r) c[r] = counts[(int64_t)(t0 + r) * kDigits + d];
-#pragma unroll
-        for (int r = 0; r < kB; ++r) {
-            offsets[(int64_t)(t0 + r) * kDigits + d] = run;
-            run += c[r];
-        }
-    }
-    for (int t = t0; t < ntiles; ++t) {
-        const uint32_t c = counts[(int64_t)t * kDigits + d];
-        offsets[(int64_t)t * kDigits + d] = run;
-        run += c;
-    }
-    // exclusive scan of the digit totals (256 values, 4 waves)
-    const int lane = d & 63, wave = d >> 6;
-    uint32_t x = run;
+// Inclusive scan of x over a 256-thread workgroup (4 wavefronts); s_w holds
+// the wavefront totals.
+__device__ __forceinline__ uint32_t block_scan_256(uint32_t x, uint32_t* s_w) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    if (lane == 63) s_tot[wave] = x;
+    if (lane == 63) s_w[wave] = x;
     __syncthreads();
-    uint32_t base = x - run;
-    for (int w = 0; w < wave; ++w) base += s_tot[w];
-    __syncthreads();
-    if (base != 0u) {
-        int t = 0;
-        for (; t + kB <= ntiles; t += kB) {
-            uint32_t o[kB];
-#pragma unroll
-            for (int r = 0; r < kB; ++r) o[r] = offsets[(int64_t)(t + r) * kDigits + d];
-#pragma unroll
-            for (int r = 0; r < kB; ++r) offsets[(int64_t)(t + r) * kDigits + d] = o[r] + base;
-        }
-        for (; t < ntiles; ++t) offsets[(int64_t)t * kDigits + d] += base;
+    for (int w = 0; w < wave; ++w) x += s_w[w];
+    return x;
+}
+
+// Per-digit scan over the tiles: workgroup d writes offsets[t][d] = number
+// of keys with digit d in tiles before t, and totals[d].  Each thread scans a
+// contiguous run of tiles.
+__global__ __launch_bounds__(kSortThreads) void k_rs_digit_scan(const uint32_t* __restrict__ counts, int ntiles,
+                                                                uint32_t* __restrict__ offsets,
+                                                                uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s_w[kSortWaves];
+    const int d = blockIdx.x;
+    const int per = (ntiles + kSortThreads - 1) / kSortThreads;
+    const int t0 = min(ntiles, (int)threadIdx.x * per), t1 = min(ntiles, t0 + per);
+    uint32_t sum = 0;
+    for (int t = t0; t < t1; ++t) sum += counts[(int64_t)t * kDigits + d];
+    const uint32_t incl = block_scan_256(sum, s_w);
+    uint32_t run = incl - sum;
+    for (int t = t0; t < t1; ++t) {
+        const uint32_t c = counts[(int64_t)t * kDigits + d];
+        offsets[(int64_t)t * kDigits + d] = run;
+        run += c;
     }
+    if (threadIdx.x == kSortThreads - 1) totals[d] = incl;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin, int64_t n,
                                                              int shift, int ntiles,
                                                              const uint32_t* __restrict__ offsets,
+                                                             const uint32_t* __restrict__ totals,
                                                              uint32_t* __restrict__ kout,
                                                              uint32_t* __restrict__ vout) {
+    static_assert(kSortThreads == kDigits, "one thread per digit");
     __shared__ uint32_t s_base[kDigits];
     __shared__ uint32_t s_wcount[kSortWaves][kDigits];
-    for (int i = threadIdx.x; i < kDigits; i += kSortThreads) {
-        s_base[i] = offsets[(int64_t)blockIdx.x * kDigits + i];
+    __shared__ uint32_t s_w[kSortWaves];
+    {
+        // start of digit d in the output: keys with a lower digit, then
+        // keys with digit d in earlier tiles
+        const int d = threadIdx.x;
+        const uint32_t tot = totals[d];
+        const uint32_t below = block_scan_256(tot, s_w) - tot;
+        s_base[d] = below + offsets[(int64_t)blockIdx.x * kDigits + d];
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) s_wcount[w][i] = 0;
+        for (int w = 0; w < kSortWaves; ++w) s_wcount[w][d] = 0;
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6;
@@ -209,7 +201,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 size_t radix_scratch_bytes(int64_t n) {
     const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, kTile));
-    return (size_t)(2 * ntiles * kDigits + 64) * sizeof(uint32_t);
+    return (size_t)(2 * ntiles * kDigits + kDigits + 64) * sizeof(uint32_t);
 }
 
 hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
@@ -220,6 +212,7 @@ hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint
     const int ntiles = (int)ceil_div(n, kTile);
     uint32_t* counts = static_cast<uint32_t*>(scratch);
     uint32_t* offs = counts + (int64_t)ntiles * kDigits;
+    uint32_t* totals = offs + (int64_t)ntiles * kDigits;
     uint32_t* kin = keys_a;
     uint32_t* vin = vals_a;
     uint32_t* kout = keys_b;
@@ -227,9 +220,10 @@ hipError_t radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * kDigitBits;
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n, shift, ntiles, counts);
-        hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(kDigits), 0, s, (const uint32_t*)counts, ntiles, offs);
+        hipLaunchKernelGGL(k_rs_digit_scan, dim3(kDigits), dim3(kSortThreads), 0, s, (const uint32_t*)counts, ntiles,
+                           offs, totals);
         hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, kin, vin, n, shift, ntiles,
-                           (const uint32_t*)offs, kout, vout);
+                           (const uint32_t*)offs, (const uint32_t*)totals, kout, vout);
         std::swap(kin, kout);
         std::swap(vin, vout);
     }

@@ -117,12 +117,53 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
     const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, inv_h);
     const float slack = cell_slack(qx, qy, qz, kMaxShell, h);
     if (fin) {
-        for (int j = l; j < 27; j += kGroup) {
+        // the lane's cells of the 27-cell block: all table slots are loaded
+        // first, so the lookups' latencies overlap
+        constexpr int kPer = (27 + kGroup - 1) / kGroup;
+        uint4 ent[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int j = l + kGroup * q;
+            ent[q] = make_uint4(kEmptyKey, 0u, 0u, 0u);
+            if (j < 27) {
+                int dx, dy, dz;
+                block_offset(j, dx, dy, dz);
+                const uint32_t key = prefix | cell_key(c.x + dx, c.y + dy, c.z + dz);
+                ent[q] = g.table[hash_slot(key, g.mask)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int j = l + kGroup * q;
+            if (j >= 27) continue;
             int dx, dy, dz;
             block_offset(j, dx, dy, dz);
             const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
             if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-            scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+            const uint32_t key = prefix | cell_key(c.x + dx, c.y + dy, c.z + dz);
+            uint32_t start = ent[q].y, cnt = ent[q].z;
+            if (ent[q].x != key) {
+                // empty slot: no such cell; another key: probe on from the next slot
+                cnt = 0;
+                if (ent[q].x != kEmptyKey) {
+                    uint32_t sl = (hash_slot(key, g.mask) + 1u) & g.mask;
+                    while (true) {
+                        const uint4 e = g.table[sl];
+                        if (e.x == key) {
+                            start = e.y;
+                            cnt = e.z;
+                            break;
+                        }
+                        if (e.x == kEmptyKey) break;
+                        sl = (sl + 1u) & g.mask;
+                    }
+                }
+            }
+            for (uint32_t i = 0; i < cnt; ++i) {
+                const float4 p = g.spts[start + i];
+                const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
+                if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+            }
         }
     }
     merge_lists<K>(top, k, l, lists);
@@ -390,11 +431,14 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, SegSet
     if (l == 0) store_raw(C, raw, sg, s);
 }
 
-// Second pass over the retry list: the same search without a gate.  The list
-// is short, so its queries are spread one per workgroup of a small block
-// first (query e goes to block e mod gridDim.x), to use every compute unit.
-// Points it cannot prove exact within kMaxShell shells go to the overflow list.
+// Second pass over the retry list: the same search under a gate of
+// kRetryGateCells cells.  The list is short, so its queries are spread one per
+// workgroup of a small block first (query e goes to block e mod gridDim.x), to
+// use every compute unit.  Points that still have fewer than k neighbours
+// inside the gate (isolated points) or whose search did not finish go to the
+// overflow list, whose whole-cloud scan needs no gate.
 constexpr int kRetryThreads = 64;
+constexpr float kRetryGateCells = 3.0f;
 
 template <int K>
 __global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, SegSet S, int k,
@@ -412,8 +456,11 @@ __global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, Seg
         const Seg sg = S.get(p);
         const float4 q = g.spts[s];
         TopK<K> top;
-        if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, FLT_MAX, FLT_MAX,
-                           top, l, s_lists[grp])) {
+        const float gate = kRetryGateCells * sg.h;
+        const float gate2 = gate * gate;
+        if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, gate2,
+                           gate * 1.000001f + 1e-6f, top, l, s_lists[grp]) ||
+            top.v[K - 1] == ~0ull) {
             if (l == 0) push_work(work, g.n, 1, s);
             continue;
         }
