@@ -239,6 +239,60 @@ int gicp_profile(gicp_ctx* ctx, int enable);
 int gicp_profile_read(gicp_ctx* ctx, int group, int64_t* launches, double* total_ms, double* units);
 
 /* ------------------------------------------------------------------------
+ * Frame preparation and map growth (Sec. 3 system overview; Sec. 3.2
+ * Keyframe Selection; Sec. 3.3 Scale Aligning)
+ * ------------------------------------------------------------------------ */
+
+/* Depth image -> tracking point cloud (Sec. 3, Fig. 2: the depth image is
+ * reprojected and downsampled).  depth: device float [height][width] in
+ * metres; a pixel is valid when 0 < z <= max_depth and finite.  Pinhole
+ * back-projection in FP32, x = (u - cx) z / fx, y = (v - cy) z / fy (each
+ * operation rounded on its own); every occupied voxel (floor(x/voxel),
+ * floor(y/voxel), floor(z/voxel)) yields the FP64 centroid of its points,
+ * rounded to FP32.  Output: out_xyz, device SoA [3][*n_out] (stride *n_out),
+ * voxels sorted by (ix, iy, iz); *n_out (host) the count.  Synchronises the
+ * stream twice.  GICP_E_ARG when the count would exceed `capacity` points or
+ * the occupied voxel box exceeds 2^32 - 1 voxels. */
+int gicp_depth_to_points(gicp_ctx* ctx, const float* depth, int width, int height, float fx, float fy, float cx,
+                         float cy, float voxel, float max_depth, float* out_xyz, int64_t capacity, int64_t* n_out,
+                         void* stream);
+
+/* The Gaussians a keyframe adds to the map (Sec. 3.2: only Gaussians that do
+ * not overlap the current map; Sec. 3.3: scale aligning Lambda'' = Lambda' /
+ * z^p, i.e. C'' = C' / z^(2p) with z the camera-frame depth).  src [3][n] and
+ * src_covs [6][n] (device) are the frame's points and regularised
+ * covariances in the camera frame; pose (host double[16]) maps camera to map.
+ * A point overlaps when R x + t has a map mean within r_overlap (the FP32
+ * correspondence test of the registration).  The non-overlapping points are
+ * written in point order to out_means [3][n] / out_covs [6][n] (device, SoA
+ * with stride n) as mu = R x + t and C = R C'' R^T (FP64 arithmetic); *n_out
+ * (host) is their count and *inlier_ratio (host, nullable) the fraction of
+ * points with a correspondence.  Synchronises the stream. */
+int gicp_keyframe_gaussians(gicp_ctx* ctx, const float* src, const float* src_covs, int64_t n, const gicp_map* map,
+                            const double pose[16], float r_overlap, float p, float* out_means, float* out_covs,
+                            int64_t* n_out, double* inlier_ratio, void* stream);
+
+/* Keyframe decision (Sec. 3.2 and Sec. 3.3, Additional Keyframe Selection for
+ * Mapping): GICP_KEYFRAME when the correspondence ratio is below `threshold`
+ * or `since_keyframe` >= max_gap (> 0); otherwise GICP_MAPPING_ONLY when
+ * `since_mapping` (frames since the last keyframe of either kind) >=
+ * mapping_gap (> 0); else 0.  Host-only. */
+enum { GICP_KEYFRAME = 1, GICP_MAPPING_ONLY = 2 };
+int gicp_keyframe_policy(double inlier_ratio, int since_keyframe, int since_mapping, double threshold, int max_gap,
+                         int mapping_gap);
+
+/* Adds m_new Gaussians (means [3][m_new], covariances [6][m_new], device,
+ * map frame) to a map without re-sorting it: the new points are sorted on
+ * their own and merged into the map's cell order (old points first among
+ * equal cells), and the cell table is rebuilt from the merged keys.  Their
+ * covariances get the regularisation the map was built with.  The result
+ * equals gicp_map_build of the concatenation [old; new] (indices of new
+ * points continue after the old ones).  May synchronise the stream when the
+ * map's arrays grow. */
+int gicp_map_insert(gicp_ctx* ctx, gicp_map* map, const float* means, const float* covs, int64_t m_new,
+                    void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned warm start (an extension: the paper starts every registration from
  * the previous pose).  A PointNet-style regressor maps a frame pair to its
  * relative pose, used as the initial pose of the registration; callers fall

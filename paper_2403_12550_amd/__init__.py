@@ -203,6 +203,56 @@ class Context:
         return RegisterResult(np.array(pose[:]).reshape(4, 4), np.array(H[:]).reshape(6, 6), np.array(b[:]),
                               stats.iters, stats.n_inliers, stats.cost, bool(stats.converged), st)
 
+    def depth_to_points(self, depth, fx, fy, cx, cy, voxel=0.02, max_depth=1e4):
+        """depth: [H, W] float32 CUDA tensor (metres) -> voxel centroids [3, n] (camera frame)."""
+        import torch
+        if depth.dtype != torch.float32 or not depth.is_cuda or depth.dim() != 2 or not depth.is_contiguous():
+            raise ValueError("depth must be a contiguous float32 CUDA tensor [H, W]")
+        H, W = depth.shape
+        buf = torch.empty(3 * H * W, dtype=torch.float32, device=depth.device)
+        n = C.c_int64()
+        st = lib().gicp_depth_to_points(self.handle, _ptr(depth), W, H, fx, fy, cx, cy, voxel, max_depth, _ptr(buf),
+                                        H * W, C.byref(n), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_depth_to_points")
+        return buf[:3 * n.value].view(3, n.value)
+
+    def keyframe_gaussians(self, src, src_covs, gmap: Map, pose, r_overlap=0.1, p=1.5):
+        """Gaussians a keyframe adds (non-overlapping points, scale aligned, in
+        the map frame): (means [3, m], covs [6, m], inlier ratio)."""
+        import torch
+        _check_f32_cuda(src, 3, "src")
+        _check_f32_cuda(src_covs, 6, "src_covs")
+        n = src.shape[1]
+        means = torch.empty((3, n), dtype=torch.float32, device=src.device)
+        covs = torch.empty((6, n), dtype=torch.float32, device=src.device)
+        m = C.c_int64()
+        ratio = C.c_double()
+        T = _abi.D16(*np.asarray(pose, np.float64).reshape(16))
+        st = lib().gicp_keyframe_gaussians(self.handle, _ptr(src), _ptr(src_covs), n, gmap.handle, T, r_overlap, p,
+                                           _ptr(means), _ptr(covs), C.byref(m), C.byref(ratio), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_keyframe_gaussians")
+        k = m.value
+        # the outputs use stride n; return compact [3, k] / [6, k] views' copies
+        return means[:, :k].contiguous(), covs[:, :k].contiguous(), ratio.value
+
+    def map_insert(self, gmap: Map, means, covs):
+        _check_f32_cuda(means, 3, "means")
+        _check_f32_cuda(covs, 6, "covs")
+        st = lib().gicp_map_insert(self.handle, gmap.handle, _ptr(means), _ptr(covs), means.shape[1], _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_map_insert")
+        m = C.c_int64()
+        c = C.c_float()
+        lib().gicp_map_info(gmap.handle, C.byref(m), C.byref(c))
+        gmap.m = int(m.value)
+        return gmap
+
+    @staticmethod
+    def keyframe_policy(ratio, since_keyframe, since_mapping, threshold, max_gap=30, mapping_gap=10):
+        return int(lib().gicp_keyframe_policy(ratio, since_keyframe, since_mapping, threshold, max_gap, mapping_gap))
+
     def register_batch(self, problems, prm: Params | None = None):
         """problems: sequence of (src [3,n], src_covs [6,n] or None, Map, init_pose 4x4).
         Returns a list of RegisterResult (one per problem)."""

@@ -94,6 +94,12 @@ SIGNATURES = {
                                       C.POINTER(Stats), P]),
     "gicp_profile": (C.c_int, [P, C.c_int]),
     "gicp_profile_read": (C.c_int, [P, C.c_int, C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gicp_depth_to_points": (C.c_int, [P, P, C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
+                                       C.c_float, C.c_float, P, I64, C.POINTER(I64), P]),
+    "gicp_keyframe_gaussians": (C.c_int, [P, P, P, I64, P, D16, C.c_float, C.c_float, P, P, C.POINTER(I64),
+                                          C.POINTER(C.c_double), P]),
+    "gicp_keyframe_policy": (C.c_int, [C.c_double, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int]),
+    "gicp_map_insert": (C.c_int, [P, P, P, P, I64, P]),
     "gicp_mlp_init": (C.c_int, [P, C.c_uint64, P, P, P, P, P]),
     "gicp_mlp_sync_weights": (C.c_int, [P, P, P, P]),
     "gicp_mlp_pack": (C.c_int, [P, C.c_int, C.POINTER(MlpPair), P, P, P]),
@@ -103,6 +109,7 @@ SIGNATURES = {
 }
 
 PROF_LINEARIZE, PROF_KNN_COV, PROF_GRID, PROF_SOLVE = 0, 1, 2, 3
+KEYFRAME, MAPPING_ONLY = 1, 2
 
 _lib = None
 

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgicp.so")
-SOURCES = ["grid.hip", "knn.hip", "gn.hip", "mlp.hip", "batch.hip", "api.hip"]
+SOURCES = ["grid.hip", "knn.hip", "gn.hip", "mlp.hip", "depth.hip", "api.hip"]
 ARCH = os.environ.get("GICP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

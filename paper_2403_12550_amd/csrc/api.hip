@@ -90,6 +90,8 @@ struct gicp_ctx {
     hipEvent_t pairs_ev = nullptr;      // recorded after the last upload of h_pairs
     bool pairs_pending = false;
     Buf mlp_pairs, mlp_pmax, mlp_parg, mlp_gpair, mlp_lpair;
+    // depth, keyframe and map-insert workspaces
+    Buf dep_pts, dep_vox, dep_flags, dep_pos, dep_scan, dep_misc, ins_cov;
     double queue_units = 0.0;        // source points x iterations of the last queue launch
     std::vector<double> iter_units;  // per iteration: source points of the problems still running
     // kernel timing
@@ -105,11 +107,18 @@ struct gicp_ctx {
 struct gicp_map {
     int device = 0;
     int64_t m = 0;
+    int64_t cap = 0;                 // points the arrays below hold
     float h = 0.f;
     uint32_t mask = 0;
-    float4* spts = nullptr;
-    uint4* table = nullptr;
-    float4* scov = nullptr;
+    int reg_mode = GICP_REG_NONE;    // applied to inserted covariances as at the build
+    float eps = 1e-3f;
+    float4* spts = nullptr;          // [cap] cell-sorted x, y, z, index
+    uint4* table = nullptr;          // [mask + 1]
+    float4* scov = nullptr;          // [2 cap] regularised covariances in cell order
+    uint32_t* keys = nullptr;        // [cap] cell keys in cell order
+    float4* spts2 = nullptr;         // spare arrays of the same capacity (merge target of gicp_map_insert)
+    float4* scov2 = nullptr;
+    uint32_t* keys2 = nullptr;
 };
 
 namespace {
@@ -173,7 +182,7 @@ void reserve_grid(GridBufs& gb, int64_t n) {
 // radix sort (3 passes for one cloud, 4 when the cloud index is part of the
 // key), cell table and the points gathered into grid order.
 GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const SegSet& S, int64_t total, hipStream_t s,
-                    float4* spts_out = nullptr, uint4* table_out = nullptr) {
+                    float4* spts_out = nullptr, uint4* table_out = nullptr, uint32_t* keys_out = nullptr) {
     uint32_t* ka = ensure<uint32_t>(gb.keys_a, total);
     uint32_t* va = ensure<uint32_t>(gb.vals_a, total);
     uint32_t* kb = ensure<uint32_t>(gb.keys_b, total);
@@ -188,6 +197,7 @@ GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const SegSet& S, int64_t total,
     check(radix_sort(ka, va, kb, vb, total, S.count > 1 ? 4 : 3, scr, s, &ks, &vs));
     check(launch_table_clear(table, cap, s));
     check(launch_table_build(ks, vs, total, S, spts, table, cap - 1, s));
+    if (keys_out) check(hipMemcpyAsync(keys_out, ks, total * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     prof_close(ctx, pm, s);
     gb.sorted_vals = vs;
     GridView g;
@@ -345,7 +355,8 @@ int gicp_destroy(gicp_ctx* c) {
     for (Buf* b : {&c->grid.keys_a, &c->grid.vals_a, &c->grid.keys_b, &c->grid.vals_b, &c->grid.scratch,
                    &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
                    &c->nn_prev, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
-                   &c->mlp_lpair})
+                   &c->mlp_lpair, &c->dep_pts, &c->dep_vox, &c->dep_flags, &c->dep_pos, &c->dep_scan, &c->dep_misc,
+                   &c->ins_cov})
         release(*b);
     if (c->h_pairs) (void)hipHostFree(c->h_pairs);
     if (c->pairs_ev) (void)hipEventDestroy(c->pairs_ev);
@@ -452,12 +463,16 @@ int gicp_map_build(gicp_ctx* c, const float* means, const float* covs, int64_t m
         const uint32_t cap = table_capacity(m);
         mp->device = c->device;
         mp->m = m;
+        mp->cap = m;
         mp->h = h;
         mp->mask = cap - 1;
+        mp->reg_mode = reg_mode;
+        mp->eps = eps;
         check(hipMalloc(&mp->spts, m * sizeof(float4)));
         check(hipMalloc(&mp->table, (size_t)cap * sizeof(uint4)));
         check(hipMalloc(&mp->scov, 2 * m * sizeof(float4)));
-        build_grid(c, c->grid, one_cloud(means, m, h), m, s, mp->spts, mp->table);
+        check(hipMalloc(&mp->keys, m * sizeof(uint32_t)));
+        build_grid(c, c->grid, one_cloud(means, m, h), m, s, mp->spts, mp->table, mp->keys);
         check(launch_map_covs(c->grid.sorted_vals, m, covs, m, reg_mode, eps, mp->scov, c->d_err, s));
         *out = mp;
         return GICP_OK;
@@ -474,6 +489,10 @@ int gicp_map_destroy(gicp_map* mp) {
     if (mp->spts) (void)hipFree(mp->spts);
     if (mp->table) (void)hipFree(mp->table);
     if (mp->scov) (void)hipFree(mp->scov);
+    if (mp->keys) (void)hipFree(mp->keys);
+    if (mp->spts2) (void)hipFree(mp->spts2);
+    if (mp->scov2) (void)hipFree(mp->scov2);
+    if (mp->keys2) (void)hipFree(mp->keys2);
     delete mp;
     return GICP_OK;
 }
@@ -947,6 +966,199 @@ int gicp_mlp_adam_step(gicp_ctx* c, float* params, float* m, float* v, const flo
     try {
         check(hipSetDevice(c->device));
         check(launch_mlp_adam(params, m, v, grad, t, lr, wbf16, (hipStream_t)stream));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// depth image -> point cloud; keyframe Gaussians; incremental map update
+// ---------------------------------------------------------------------------
+int gicp_depth_to_points(gicp_ctx* c, const float* depth, int width, int height, float fx, float fy, float cx,
+                         float cy, float voxel, float max_depth, float* out_xyz, int64_t capacity, int64_t* n_out,
+                         void* stream) {
+    if (!c || !depth || !out_xyz || !n_out || width < 1 || height < 1 || !(voxel > 0.f) || !(fx != 0.f) ||
+        !(fy != 0.f) || !(max_depth > 0.f) || (int64_t)width * height >= (1ll << 31))
+        return GICP_E_ARG;
+    *n_out = 0;
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = (int64_t)width * height;
+        float* pts = ensure<float>(c->dep_pts, 3 * n);
+        int* vox = ensure<int>(c->dep_vox, 3 * n);
+        int* misc = ensure<int>(c->dep_misc, 64);   // [0..6) bounds, [8] voxel count
+        check(launch_depth_points(depth, width, height, fx, fy, cx, cy, voxel, max_depth, pts, vox, misc, s));
+        int hb[6];
+        check(hipMemcpyAsync(c->h_err + 8, misc, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+        check(hipStreamSynchronize(s));
+        std::memcpy(hb, c->h_err + 8, sizeof(hb));
+        if (hb[0] > hb[3]) return GICP_OK;   // no valid pixel
+        const uint64_t dx = (uint64_t)((int64_t)hb[3] - hb[0] + 1), dy = (uint64_t)((int64_t)hb[4] - hb[1] + 1),
+                       dz = (uint64_t)((int64_t)hb[5] - hb[2] + 1);
+        const double cells = (double)dx * (double)dy * (double)dz;
+        if (cells >= 4294967295.0) return GICP_E_ARG;   // occupied box exceeds 32-bit voxel keys
+        const uint64_t total = dx * dy * dz;
+        int passes = 1;
+        while (passes < 4 && (1ull << (8 * passes)) - 1 <= total) ++passes;
+        GridBufs& gb = c->grid;
+        uint32_t* ka = ensure<uint32_t>(gb.keys_a, n);
+        uint32_t* va = ensure<uint32_t>(gb.vals_a, n);
+        uint32_t* kb = ensure<uint32_t>(gb.keys_b, n);
+        uint32_t* vb = ensure<uint32_t>(gb.vals_b, n);
+        void* scr = ensure<uint8_t>(gb.scratch, radix_scratch_bytes(n));
+        check(launch_voxel_keys(vox, n, misc, (uint32_t)dy, (uint32_t)dz, ka, va, s));
+        uint32_t *ks = nullptr, *vs = nullptr;
+        check(radix_sort(ka, va, kb, vb, n, passes, scr, s, &ks, &vs));
+        uint32_t* flags = ensure<uint32_t>(c->dep_flags, n);
+        uint32_t* pos = ensure<uint32_t>(c->dep_pos, n);
+        void* sscr = ensure<uint8_t>(c->dep_scan, flag_scan_scratch(n));
+        check(launch_voxel_starts(ks, n, flags, s));
+        check(launch_flag_scan(flags, n, pos, reinterpret_cast<uint32_t*>(misc + 8), sscr, s));
+        check(hipMemcpyAsync(c->h_err + 8, misc + 8, sizeof(int), hipMemcpyDeviceToHost, s));
+        check(hipStreamSynchronize(s));
+        const int64_t m = (int64_t)(uint32_t)c->h_err[8];
+        if (m > capacity) return GICP_E_ARG;
+        check(launch_voxel_centroids(ks, vs, n, flags, pos, pts, out_xyz, m, s));
+        *n_out = m;
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_keyframe_gaussians(gicp_ctx* c, const float* src, const float* src_covs, int64_t n, const gicp_map* map,
+                            const double pose[16], float r_overlap, float p, float* out_means, float* out_covs,
+                            int64_t* n_out, double* inlier_ratio, void* stream) {
+    if (!c || !src || !src_covs || !map || !pose || !out_means || !out_covs || !n_out || n < 1 ||
+        !(r_overlap > 0.f) || !std::isfinite(p) || n >= (1ll << 31))
+        return GICP_E_ARG;
+    *n_out = 0;
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        gicp_params prm;
+        gicp_params_default(&prm);
+        prm.r_max = r_overlap;
+        const MapView mv = map_view(map, &prm);
+        Pose32 T32;
+        Pose64 T64;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) {
+                T32.R[3 * i + j] = (float)pose[4 * i + j];
+                T64.R[3 * i + j] = pose[4 * i + j];
+            }
+            T32.t[i] = (float)pose[4 * i + 3];
+            T64.t[i] = pose[4 * i + 3];
+        }
+        uint32_t* keep = ensure<uint32_t>(c->dep_flags, n);
+        uint32_t* pos = ensure<uint32_t>(c->dep_pos, n);
+        void* sscr = ensure<uint8_t>(c->dep_scan, flag_scan_scratch(n));
+        int* misc = ensure<int>(c->dep_misc, 64);
+        check(launch_overlap(mv, src, n, T32, keep, s));
+        check(launch_flag_scan(keep, n, pos, reinterpret_cast<uint32_t*>(misc + 8), sscr, s));
+        check(launch_keyframe_gaussians(src, src_covs, n, keep, pos, T64, 2.0 * (double)p, out_means, out_covs, s));
+        check(hipMemcpyAsync(c->h_err + 8, misc + 8, sizeof(int), hipMemcpyDeviceToHost, s));
+        check(hipStreamSynchronize(s));
+        const int64_t kept = (int64_t)(uint32_t)c->h_err[8];
+        *n_out = kept;
+        if (inlier_ratio) *inlier_ratio = (double)(n - kept) / (double)n;
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_keyframe_policy(double inlier_ratio, int since_keyframe, int since_mapping, double threshold, int max_gap,
+                         int mapping_gap) {
+    if (inlier_ratio < threshold || (max_gap > 0 && since_keyframe >= max_gap)) return GICP_KEYFRAME;
+    if (mapping_gap > 0 && since_mapping >= mapping_gap) return GICP_MAPPING_ONLY;
+    return 0;
+}
+
+int gicp_map_insert(gicp_ctx* c, gicp_map* mp, const float* means, const float* covs, int64_t m_new, void* stream) {
+    if (!c || !mp || !means || !covs || m_new < 1 || mp->m + m_new >= (1ll << 31)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t m_old = mp->m, total = m_old + m_new;
+        // 1. the new points sorted by cell key on their own, their regularised covariances in that order
+        GridBufs& gb = c->grid;
+        uint32_t* ka = ensure<uint32_t>(gb.keys_a, m_new);
+        uint32_t* va = ensure<uint32_t>(gb.vals_a, m_new);
+        uint32_t* kb = ensure<uint32_t>(gb.keys_b, m_new);
+        uint32_t* vb = ensure<uint32_t>(gb.vals_b, m_new);
+        void* scr = ensure<uint8_t>(gb.scratch, radix_scratch_bytes(m_new));
+        check(launch_cell_keys(one_cloud(means, m_new, mp->h), m_new, ka, va, c->d_err, s));
+        uint32_t *ks = nullptr, *vs = nullptr;
+        check(radix_sort(ka, va, kb, vb, m_new, 3, scr, s, &ks, &vs));
+        float4* ncov = ensure<float4>(c->ins_cov, 2 * m_new);
+        check(launch_map_covs(vs, m_new, covs, m_new, mp->reg_mode, mp->eps, ncov, c->d_err, s));
+        // 2. merge into the spare arrays (grown together with the primary
+        //    ones when the map outgrows them), then swap
+        float4 *spts = mp->spts2, *scov = mp->scov2;
+        uint32_t* keys = mp->keys2;
+        int64_t cap = mp->cap;
+        const bool grow = total > cap || !spts;
+        if (grow) {
+            cap = total > mp->cap ? std::max<int64_t>(total, mp->cap + mp->cap / 2) : mp->cap;
+            spts = nullptr;
+            scov = nullptr;
+            keys = nullptr;
+            try {
+                check(hipMalloc(&spts, cap * sizeof(float4)));
+                check(hipMalloc(&scov, 2 * cap * sizeof(float4)));
+                check(hipMalloc(&keys, cap * sizeof(uint32_t)));
+            } catch (const HipError&) {
+                if (spts) (void)hipFree(spts);
+                if (scov) (void)hipFree(scov);
+                if (keys) (void)hipFree(keys);
+                throw;
+            }
+        }
+        uint4* table = mp->table;
+        uint32_t tcap = mp->mask + 1;
+        if (table_capacity(total) > tcap) {
+            tcap = table_capacity(total);
+            table = nullptr;
+            check(hipMalloc(&table, (size_t)tcap * sizeof(uint4)));
+        }
+        check(launch_map_merge(mp->keys, mp->spts, mp->scov, m_old, ks, vs, means, ncov, m_new, keys, spts, scov, s));
+        check(launch_table_clear(table, tcap, s));
+        check(launch_table_runs(keys, total, table, tcap - 1, s));
+        if (table != mp->table) {
+            check(hipStreamSynchronize(s));
+            (void)hipFree(mp->table);
+        }
+        if (grow) {
+            // the old primary arrays were the merge source: free them after the merge,
+            // and give the map a spare set of the new capacity
+            check(hipStreamSynchronize(s));
+            (void)hipFree(mp->spts);
+            (void)hipFree(mp->scov);
+            (void)hipFree(mp->keys);
+            if (mp->spts2) (void)hipFree(mp->spts2);
+            if (mp->scov2) (void)hipFree(mp->scov2);
+            if (mp->keys2) (void)hipFree(mp->keys2);
+            mp->spts2 = nullptr;
+            mp->scov2 = nullptr;
+            mp->keys2 = nullptr;
+            mp->spts = spts;
+            mp->scov = scov;
+            mp->keys = keys;
+            check(hipMalloc(&mp->spts2, cap * sizeof(float4)));
+            check(hipMalloc(&mp->scov2, 2 * cap * sizeof(float4)));
+            check(hipMalloc(&mp->keys2, cap * sizeof(uint32_t)));
+        } else {
+            std::swap(mp->spts, mp->spts2);
+            std::swap(mp->scov, mp->scov2);
+            std::swap(mp->keys, mp->keys2);
+        }
+        mp->table = table;
+        mp->mask = tcap - 1;
+        mp->m = total;
+        mp->cap = cap;
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);

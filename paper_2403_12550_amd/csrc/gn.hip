@@ -621,6 +621,52 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev*
     solve_state(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, P.st);
 }
 
+// ---------------------------------------------------------------------------
+// Keyframe Gaussians (Sec. 3.2, Keyframe Selection; Sec. 3.3, Scale Aligning)
+// ---------------------------------------------------------------------------
+// keep[i] = 1 when R x_i + t has no map mean within r_max (the point adds a
+// new Gaussian), 0 when it has a correspondence.  kGroup lanes per point.
+__global__ __launch_bounds__(kBlock) void k_overlap(MapView m, const float* __restrict__ src, int64_t n, Pose32 T,
+                                                   uint32_t* __restrict__ keep) {
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup;
+    if (i >= n) return;   // uniform over each lane group
+    const float x = src[i], y = src[n + i], z = src[2 * n + i];
+    const float qx = T.R[0] * x + T.R[1] * y + T.R[2] * z + T.t[0];
+    const float qy = T.R[3] * x + T.R[4] * y + T.R[5] * z + T.t[1];
+    const float qz = T.R[6] * x + T.R[7] * y + T.R[8] * z + T.t[2];
+    const int32_t pos = nearest(m, qx, qy, qz, l, -1);
+    if (l == 0) keep[i] = pos < 0 ? 1u : 0u;
+}
+
+// The kept points, scale aligned in the camera frame (C / z^(2p), z the
+// depth) and moved into the map frame (mu = R x + t, C = R C R^T), in FP64,
+// written in point order at their compacted positions.
+__global__ void k_keyframe_gaussians(const float* __restrict__ src, const float* __restrict__ covs, int64_t n,
+                                     const uint32_t* __restrict__ keep, const uint32_t* __restrict__ pos, Pose64 T,
+                                     double two_p, float* __restrict__ out_means, float* __restrict__ out_covs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !keep[i]) return;
+    const int64_t o = pos[i];
+    const double x = src[i], y = src[n + i], z = src[2 * n + i];
+    const double* R = T.R;
+    out_means[o] = (float)(R[0] * x + R[1] * y + R[2] * z + T.t[0]);
+    out_means[n + o] = (float)(R[3] * x + R[4] * y + R[5] * z + T.t[1]);
+    out_means[2 * n + o] = (float)(R[6] * x + R[7] * y + R[8] * z + T.t[2]);
+    const double sc = z > 0.0 ? pow(z, -two_p) : 1.0;
+    const double C[9] = {covs[i] * sc,         covs[n + i] * sc,     covs[2 * n + i] * sc,
+                         covs[n + i] * sc,     covs[3 * n + i] * sc, covs[4 * n + i] * sc,
+                         covs[2 * n + i] * sc, covs[4 * n + i] * sc, covs[5 * n + i] * sc};
+    double RC[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) RC[3 * a + b] = R[3 * a] * C[b] + R[3 * a + 1] * C[3 + b] + R[3 * a + 2] * C[6 + b];
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; ++e) {
+        const int a = ia[e], b = ib[e];
+        out_covs[e * n + o] = (float)(RC[3 * a] * R[3 * b] + RC[3 * a + 1] * R[3 * b + 1] + RC[3 * a + 2] * R[3 * b + 2]);
+    }
+}
+
 }  // namespace
 
 int gn_blocks(int64_t n) {
@@ -708,6 +754,23 @@ hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, const int3
 
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_gn_solve, dim3(1), dim3(kSolveThreads), 0, s, partials, nblocks, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap(const MapView& m, const float* src, int64_t n, const Pose32& T, uint32_t* keep,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int per = kBlock / kGroup;
+    hipLaunchKernelGGL(k_overlap, dim3((unsigned)((n + per - 1) / per)), dim3(kBlock), 0, s, m, src, n, T, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_keyframe_gaussians(const float* src, const float* covs, int64_t n, const uint32_t* keep,
+                                     const uint32_t* pos, const Pose64& T, double two_p, float* out_means,
+                                     float* out_covs, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keyframe_gaussians, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, covs, n, keep,
+                       pos, T, two_p, out_means, out_covs);
     return hipGetLastError();
 }
 

@@ -195,6 +195,133 @@ __global__ void k_table_build(const uint32_t* __restrict__ skeys, const uint32_t
     }
 }
 
+// ---------------------------------------------------------------------------
+// Incremental map update: the new points, sorted by cell key on their own,
+// are merged into the map's sorted run.  An old point moves forward by the
+// number of new keys below its key, a new point by the number of old keys at
+// or below its key, so equal keys keep the old points first (the order a
+// stable sort of the concatenation [old; new] would give).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t count_below(const uint32_t* __restrict__ a, int64_t n, uint32_t key, bool or_equal) {
+    int64_t lo = 0, hi = n;   // first index whose key is above (or at) `key`
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const bool before = or_equal ? (a[mid] <= key) : (a[mid] < key);
+        if (before) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_merge_old(const uint32_t* __restrict__ okeys, const float4* __restrict__ opts,
+                            const float4* __restrict__ ocov, int64_t m_old, const uint32_t* __restrict__ nkeys,
+                            int64_t m_new, uint32_t* __restrict__ keys, float4* __restrict__ pts,
+                            float4* __restrict__ cov) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m_old) return;
+    const uint32_t k = okeys[i];
+    const int64_t o = i + count_below(nkeys, m_new, k, false);
+    keys[o] = k;
+    pts[o] = opts[i];
+    cov[2 * o] = ocov[2 * i];
+    cov[2 * o + 1] = ocov[2 * i + 1];
+}
+
+__global__ void k_merge_new(const uint32_t* __restrict__ nkeys, const uint32_t* __restrict__ nvals,
+                            const float* __restrict__ means, const float4* __restrict__ ncov, int64_t m_new,
+                            const uint32_t* __restrict__ okeys, int64_t m_old, uint32_t* __restrict__ keys,
+                            float4* __restrict__ pts, float4* __restrict__ cov) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_new) return;
+    const uint32_t k = nkeys[j];
+    uint32_t v = nvals[j];
+    if (v >= (uint64_t)m_new) v = 0;   // always a permutation; guards the gather
+    const int64_t o = j + count_below(okeys, m_old, k, true);
+    keys[o] = k;
+    pts[o] = make_float4(means[v], means[m_new + v], means[2 * m_new + v], __uint_as_float((uint32_t)(m_old + v)));
+    cov[2 * o] = ncov[2 * j];
+    cov[2 * o + 1] = ncov[2 * j + 1];
+}
+
+// Cell table from sorted keys alone (the points are already in place).
+__global__ void k_table_runs(const uint32_t* __restrict__ skeys, int64_t total, uint4* __restrict__ table,
+                             uint32_t mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const uint32_t key = skeys[i];
+    if (i > 0 && skeys[i - 1] == key) return;
+    uint32_t cnt = 1;
+    while (i + cnt < total && skeys[i + cnt] == key) ++cnt;
+    uint32_t s = hash_slot(key, mask);
+    while (true) {
+        const uint32_t prev = atomicCAS(&table[s].x, kEmptyKey, key);
+        if (prev == kEmptyKey) {
+            table[s].y = (uint32_t)i;
+            table[s].z = cnt;
+            break;
+        }
+        s = (s + 1u) & mask;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of 0/1 flags (stream compaction): per-tile sums, one
+// workgroup scanning the tile sums, then per-tile block scans.
+// ---------------------------------------------------------------------------
+constexpr int kScanTile = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const uint32_t* __restrict__ flags, int64_t n,
+                                                   uint32_t* __restrict__ tile_sums) {
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t sum = 0;
+    for (int r = 0; r < kScanTile / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) sum += flags[i];
+    }
+    const uint32_t incl = block_scan_256(sum, s_w);
+    if (threadIdx.x == 255) tile_sums[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ tile_sums, int64_t ntiles,
+                                                 uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t b = 0; b < ntiles; b += 256) {
+        const int64_t i = b + threadIdx.x;
+        const uint32_t x = i < ntiles ? tile_sums[i] : 0u;
+        const uint32_t incl = block_scan_256(x, s_w);
+        const uint32_t carry = s_carry;
+        if (i < ntiles) tile_sums[i] = carry + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 255) s_carry = carry + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = s_carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ flags, int64_t n,
+                                                   const uint32_t* __restrict__ tile_offs,
+                                                   uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = tile_offs[blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int r = 0; r < kScanTile / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        const uint32_t x = i < n ? flags[i] : 0u;
+        const uint32_t incl = block_scan_256(x, s_w);
+        const uint32_t carry = s_carry;
+        if (i < n) out[i] = carry + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 255) s_carry = carry + incl;
+        __syncthreads();
+    }
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -249,6 +376,36 @@ hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int6
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_table_build, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, skeys, svals, total, S,
                        spts, table, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_merge(const uint32_t* okeys, const float4* opts, const float4* ocov, int64_t m_old,
+                            const uint32_t* nkeys, const uint32_t* nvals, const float* means, const float4* ncov,
+                            int64_t m_new, uint32_t* keys, float4* pts, float4* cov, hipStream_t s) {
+    if (m_old > 0)
+        hipLaunchKernelGGL(k_merge_old, dim3((unsigned)ceil_div(m_old, 256)), dim3(256), 0, s, okeys, opts, ocov, m_old,
+                           nkeys, m_new, keys, pts, cov);
+    if (m_new > 0)
+        hipLaunchKernelGGL(k_merge_new, dim3((unsigned)ceil_div(m_new, 256)), dim3(256), 0, s, nkeys, nvals, means, ncov,
+                           m_new, okeys, m_old, keys, pts, cov);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_runs(const uint32_t* skeys, int64_t total, uint4* table, uint32_t mask, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_table_runs, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, skeys, total, table, mask);
+    return hipGetLastError();
+}
+
+size_t flag_scan_scratch(int64_t n) { return (size_t)(ceil_div(std::max<int64_t>(n, 1), kScanTile) + 64) * 4; }
+
+hipError_t launch_flag_scan(const uint32_t* flags, int64_t n, uint32_t* out, uint32_t* total, void* scratch,
+                            hipStream_t s) {
+    const int64_t ntiles = ceil_div(std::max<int64_t>(n, 1), kScanTile);
+    uint32_t* tiles = static_cast<uint32_t*>(scratch);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, s, flags, n, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, tiles, ntiles, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(256), 0, s, flags, n, (const uint32_t*)tiles, out);
     return hipGetLastError();
 }
 

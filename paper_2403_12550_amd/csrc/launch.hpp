@@ -151,6 +151,46 @@ hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks,
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
 
+// Incremental map update (grid.hip): merge the map's sorted run (okeys,
+// opts, ocov; m_old) with new points sorted on their own (nkeys, nvals into
+// means [3][m_new], regularised covariances ncov in that sorted order) into
+// (keys, pts, cov) of m_old + m_new entries; equal keys keep old points first.
+hipError_t launch_map_merge(const uint32_t* okeys, const float4* opts, const float4* ocov, int64_t m_old,
+                            const uint32_t* nkeys, const uint32_t* nvals, const float* means, const float4* ncov,
+                            int64_t m_new, uint32_t* keys, float4* pts, float4* cov, hipStream_t s);
+// Cell table from sorted keys (points already in cell order); table cleared by the caller.
+hipError_t launch_table_runs(const uint32_t* skeys, int64_t total, uint4* table, uint32_t mask, hipStream_t s);
+// Exclusive scan of 0/1 flags; *total (device) receives the sum.
+size_t flag_scan_scratch(int64_t n);
+hipError_t launch_flag_scan(const uint32_t* flags, int64_t n, uint32_t* out, uint32_t* total, void* scratch,
+                            hipStream_t s);
+
+// Keyframe Gaussians (gn.hip).
+struct Pose32 {
+    float R[9], t[3];
+};
+struct Pose64 {
+    double R[9], t[3];
+};
+// keep[i] = 1 when R x_i + t has no map mean within m.r_max.
+hipError_t launch_overlap(const MapView& m, const float* src, int64_t n, const Pose32& T, uint32_t* keep,
+                          hipStream_t s);
+// Kept points -> map-frame means and scale-aligned, rotated covariances at
+// out[pos[i]] (SoA with stride n).
+hipError_t launch_keyframe_gaussians(const float* src, const float* covs, int64_t n, const uint32_t* keep,
+                                     const uint32_t* pos, const Pose64& T, double two_p, float* out_means,
+                                     float* out_covs, hipStream_t s);
+
+// Depth image -> voxel centroids (depth.hip).  pts [3][W*H], vox [3][W*H],
+// bounds [8] ints.
+hipError_t launch_depth_points(const float* depth, int W, int H, float fx, float fy, float cx, float cy, float voxel,
+                               float max_depth, float* pts, int* vox, int* bounds, hipStream_t s);
+hipError_t launch_voxel_keys(const int* vox, int64_t n, const int* bounds, uint32_t dy, uint32_t dz, uint32_t* keys,
+                             uint32_t* vals, hipStream_t s);
+hipError_t launch_voxel_starts(const uint32_t* skeys, int64_t n, uint32_t* flags, hipStream_t s);
+hipError_t launch_voxel_centroids(const uint32_t* skeys, const uint32_t* svals, int64_t n, const uint32_t* flags,
+                                  const uint32_t* pos, const float* pts, float* out, int64_t m, hipStream_t s);
+
 // Warm-start network (mlp.hip).
 hipError_t launch_mlp_init(uint64_t seed, float* params, float* m, float* v, uint16_t* wb, hipStream_t s);
 hipError_t launch_mlp_fragments(const float* params, uint16_t* wb, hipStream_t s);

@@ -86,6 +86,11 @@ class C2Sequence:
             self._frames[i] = pts.astype(np.float32)
         return self._frames[i]
 
+    def depth(self, i: int) -> np.ndarray:
+        """Depth image [H, W] float32 of frame i (noise and invalid pixels applied)."""
+        d = render_depth(self.scene, self.poses[i], self.K)
+        return corrupt_depth(d, 100 + i, 200 + i).astype(np.float32)
+
     def prefetch(self, indices, workers: int = 8):
         """Render several frames in parallel worker processes (fork)."""
         import concurrent.futures as cf
