@@ -141,6 +141,11 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=4, help="frames the CPU oracle baseline registers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--c4", action="store_true", help="also time the 64-problem batch workload")
+    ap.add_argument("--no-frontend", action="store_true",
+                    help="skip the depth-to-points and keyframe-insertion timings")
+    ap.add_argument("--regularisation-study", type=int, default=0, metavar="FRAMES",
+                    help="closed-loop tracking of the first FRAMES frames with no / plane / ellipse "
+                         "regularisation of map and frame covariances; reports the trajectory error of each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "the HBM byte counters) and exit")
@@ -227,6 +232,9 @@ def main():
                 "avg_launch_us": 1e3 * ms / n}
 
     c4 = run_c4(ctx, g) if args.c4 else None
+    frontend = None if args.no_frontend else run_frontend(ctx, g, seq, means, covs, args.map_cell)
+    regst = run_regularisation_study(ctx, g, seq, means, args.map_cell, args.regularisation_study) \
+        if args.regularisation_study else None
 
     cpu = None
     err_vs_oracle = None
@@ -277,6 +285,8 @@ def main():
         "map_build_ms": round(map_ms, 3),
         "kernels": kernels,
         "c4_batch": c4,
+        "frontend": frontend,
+        "regularisation_study": regst,
     }
     print(json.dumps(out), flush=True)
     gmap.close()
@@ -326,6 +336,92 @@ def run_c4(ctx, g, n_prob=64):
     out["source_points"] = int(sum(p.src.shape[0] for p in probs))
     out["target_gaussians"] = int(sum(p.tgt.shape[0] for p in probs))
     del prm
+    return out
+
+
+def _render_depths(seq, idx, workers):
+    import multiprocessing as mp
+    if workers <= 1:
+        return [seq.depth(i) for i in idx]
+    with mp.get_context("fork").Pool(min(workers, len(idx))) as pool:
+        return pool.map(seq.depth, idx)
+
+
+def run_frontend(ctx, g, seq, means, covs, map_cell, n_depth=10):
+    """Depth image -> voxelised cloud on the GPU (1200x680 frames, 2 cm
+    voxels), and the keyframe insertion of one frame into the 1M map
+    (overlap test, scale aligning, transform, merge into the map)."""
+    import torch
+    idx = list(range(n_depth))
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    depths = [torch.from_numpy(d).cuda() for d in _render_depths(seq, idx, workers)]
+    K = seq.K
+    ctx.depth_to_points(depths[0], K.fx, K.fy, K.cx, K.cy, seq.voxel)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    npts = []
+    for d in depths:
+        npts.append(ctx.depth_to_points(d, K.fx, K.fy, K.cx, K.cy, seq.voxel).shape[1])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / len(depths)
+    out = {"depth_to_points": {"frames_per_s": round(1.0 / dt, 1), "ms_per_frame": round(1e3 * dt, 3),
+                               "mean_points": float(np.mean(npts)), "pixels": int(depths[0].numel()),
+                               "note": "includes two host synchronisations per frame (bounding box, count)"}}
+    # keyframe insertion: frame 0 at its ground-truth pose into a fresh copy of the map
+    gm = ctx.map_build(means, covs, cell=map_cell, reg_mode=g.REG_PLANE, eps=1e-3)
+    src = g.to_soa(seq.frame(0))
+    scov = ctx.covariances(src, 20, reg_mode=g.REG_ELLIPSE)
+    ctx.keyframe_gaussians(src, scov, gm, seq.poses[0], 0.02, 1.5)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        m_new, c_new, ratio = ctx.keyframe_gaussians(src, scov, gm, seq.poses[0], 0.02, 1.5)
+    torch.cuda.synchronize()
+    t_kf = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    ctx.map_insert(gm, m_new, c_new)
+    torch.cuda.synchronize()
+    t_ins = time.perf_counter() - t
+    out["keyframe_insert"] = {"frame_points": int(src.shape[1]), "inserted": int(m_new.shape[1]),
+                              "correspondence_ratio": round(ratio, 4), "keyframe_gaussians_ms": round(1e3 * t_kf, 3),
+                              "map_insert_ms": round(1e3 * t_ins, 3), "map_size_after": gm.m,
+                              "note": "r_overlap 2 cm, p = 1.5; the first insert allocates the map's spare arrays"}
+    gm.close()
+    log(f"frontend: {out}")
+    return out
+
+
+def run_regularisation_study(ctx, g, seq, means, map_cell, n_frames):
+    """The regularisation of map and frame covariances (none / plane /
+    ellipse) compared on tracking error: closed-loop tracking (constant-
+    velocity prediction from the estimated poses) of the first n_frames
+    frames, and per-frame registration from the prediction of the ground-
+    truth poses over the whole sequence."""
+    out = {"closed_loop_frames": n_frames, "open_loop_frames": len(seq)}
+    frames = [g.to_soa(seq.frame(i)) for i in range(len(seq))]
+    for name, mode in (("none", g.REG_NONE), ("plane", g.REG_PLANE), ("ellipse", g.REG_ELLIPSE)):
+        gm = ctx.map_build(means, g.to_soa(seq.map_cov_raw), cell=map_cell, reg_mode=mode, eps=1e-3)
+        prm = g.params(k=20, eps=1e-3, r_max=0.1, max_it=20, conv_rot=1e-6, conv_trans=1e-6, reg_mode=mode)
+        est, errs, iters, lost = [], [], [], 0
+        for i in range(n_frames):
+            r = ctx.register(frames[i], gm, cv_init(seq, est, i), prm)
+            est.append(r.pose)
+            iters.append(r.iters)
+            lost += int(r.status != 0)
+            errs.append(pose_delta(r.pose, seq.poses[i]))
+        e = np.array(errs)
+        res = {"closed_loop_ate_rmse_m": float(np.sqrt(np.mean(e[:, 1] ** 2))),
+               "closed_loop_max_trans_err_m": float(e[:, 1].max()), "closed_loop_failed_frames": lost,
+               "closed_loop_mean_iterations": float(np.mean(iters))}
+        e2 = np.array([pose_delta(ctx.register(frames[i], gm, cv_init(seq, seq.poses, i), prm).pose, seq.poses[i])
+                       for i in range(len(seq))])
+        res.update({"open_loop_rmse_m": float(np.sqrt(np.mean(e2[:, 1] ** 2))),
+                    "open_loop_max_trans_err_m": float(e2[:, 1].max()),
+                    "open_loop_mean_rot_err_rad": float(e2[:, 0].mean())})
+        out[name] = res
+        gm.close()
+        log(f"regularisation {name}: {res}")
     return out
 
 

@@ -102,7 +102,12 @@ enum {
     /* One persistent work-queue launch runs every iteration of every problem:
      * workers pop chunks, the last chunk of an iteration solves and posts the
      * problem's next iteration. */
-    GICP_FLAG_QUEUE = 2
+    GICP_FLAG_QUEUE = 2,
+    /* The default batched launches, with the max_it iterations recorded once
+     * into a HIP graph (per batch shape and workspace) and replayed by one
+     * graph launch.  Same kernels and results as the default form.  Kernel
+     * timing, when enabled, covers the whole replay under group 0. */
+    GICP_FLAG_GRAPH = 4
 };
 
 /* One problem of a batched registration. */

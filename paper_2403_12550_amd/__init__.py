@@ -14,11 +14,11 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_MULTI_LAUNCH, FLAG_QUEUE, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK,
+from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_GRAPH, FLAG_MULTI_LAUNCH, FLAG_QUEUE, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK,
                    Params, Problem, Stats)
 
 __all__ = ["Context", "Map", "Params", "Stats", "Problem", "RegisterResult", "GicpError", "params",
-           "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "FLAG_MULTI_LAUNCH", "FLAG_QUEUE",
+           "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "FLAG_MULTI_LAUNCH", "FLAG_QUEUE", "FLAG_GRAPH",
            "to_soa", "lib"]
 
 

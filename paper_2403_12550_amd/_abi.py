@@ -30,6 +30,7 @@ class Params(C.Structure):
 
 FLAG_MULTI_LAUNCH = 1
 FLAG_QUEUE = 2
+FLAG_GRAPH = 4
 
 
 class Problem(C.Structure):

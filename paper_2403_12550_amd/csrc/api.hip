@@ -92,6 +92,15 @@ struct gicp_ctx {
     Buf mlp_pairs, mlp_pmax, mlp_parg, mlp_gpair, mlp_lpair;
     // depth, keyframe and map-insert workspaces
     Buf dep_pts, dep_vox, dep_flags, dep_pos, dep_scan, dep_misc, ins_cov;
+    // graph-captured Gauss-Newton iterations, keyed by batch shape and workspace
+    struct GraphEntry {
+        int nprob, max_it, acc;
+        int64_t chunks;
+        const void *probs, *chunk_prob, *part;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
     double queue_units = 0.0;        // source points x iterations of the last queue launch
     std::vector<double> iter_units;  // per iteration: source points of the problems still running
     // kernel timing
@@ -358,6 +367,8 @@ int gicp_destroy(gicp_ctx* c) {
                    &c->mlp_lpair, &c->dep_pts, &c->dep_vox, &c->dep_flags, &c->dep_pos, &c->dep_scan, &c->dep_misc,
                    &c->ins_cov})
         release(*b);
+    for (auto& ge : c->graphs) (void)hipGraphExecDestroy(ge.exec);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->h_pairs) (void)hipHostFree(c->h_pairs);
     if (c->pairs_ev) (void)hipEventDestroy(c->pairs_ev);
     if (c->d_err) (void)hipFree(c->d_err);
@@ -523,7 +534,44 @@ MapView map_view(const gicp_map* map, const gicp_params* prm) {
 }
 
 bool valid_params(const gicp_params* prm) {
-    return prm && prm->max_it >= 0 && prm->r_max > 0.f && prm->precision >= 0 && prm->precision <= 2;
+    return prm && prm->max_it >= 0 && prm->r_max > 0.f && prm->precision >= 0 && prm->precision <= 2 &&
+           (prm->flags & ~(GICP_FLAG_MULTI_LAUNCH | GICP_FLAG_QUEUE | GICP_FLAG_GRAPH)) == 0;
+}
+
+// Graph of the max_it batched iterations for this batch shape and these
+// workspace addresses (captured once on a private stream, then cached).
+constexpr int64_t kGraphBucket = 1024;   // launch grids are padded to a multiple of this many chunks
+constexpr size_t kMaxGraphs = 8;
+
+hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, const int32_t* chunk_prob,
+                               double* part) {
+    for (auto& e : c->graphs)
+        if (e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc && e.probs == c->d_probs &&
+            e.chunk_prob == chunk_prob && e.part == part)
+            return e.exec;
+    if (!c->capture_stream) check(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->capture_stream;
+    hipGraph_t graph = nullptr;
+    check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int it = 0; it < max_it && err == hipSuccess; ++it) {
+        err = launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, grid, part, acc, true, false, cs);
+        if (err == hipSuccess)
+            err = launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, grid, part, acc, false, true, cs);
+    }
+    const hipError_t end = hipStreamEndCapture(cs, &graph);
+    check(err);
+    check(end);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    check(inst);
+    if (c->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({nprob, max_it, acc, grid, c->d_probs, chunk_prob, part, exec});
+    return exec;
 }
 
 // Registers nprob problems (validated by the caller).  covs_out[p] (nullable)
@@ -704,6 +752,17 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
             check(launch_gn_queue(c->d_probs, nprob, c->d_queue, items, cap, (uint32_t)chunks, arrive, part, workers,
                                   acc, s));
             prof_close(c, pq, s);
+        } else if (prm->flags & GICP_FLAG_GRAPH) {
+            check(hipMemcpyAsync(c->d_probs, c->h_probs, nprob * sizeof(ProbDev), hipMemcpyHostToDevice, s));
+            const int64_t grid = (chunks + kGraphBucket - 1) / kGraphBucket * kGraphBucket;
+            int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, grid);
+            double* part = ensure<double>(c->partials, (size_t)grid * kNumAcc);
+            check(launch_chunk_map(c->d_probs, nprob, chunk_prob, s));
+            if (grid > chunks) check(launch_fill_i32(chunk_prob + chunks, grid - chunks, -1, s));
+            hipGraphExec_t ge = iteration_graph(c, nprob, grid, prm->max_it, prm->precision, chunk_prob, part);
+            const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, -2, s);
+            check(hipGraphLaunch(ge, s));
+            prof_close(c, pl, s);
         } else {
             check(hipMemcpyAsync(c->d_probs, c->h_probs, nprob * sizeof(ProbDev), hipMemcpyHostToDevice, s));
             int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, chunks);

@@ -603,6 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_gn_linearize_batch(const ProbDev* __
                                                                double* __restrict__ partials) {
     const int b = blockIdx.x;
     const int p = chunk_prob[b];
+    if (p < 0) return;   // padding of a graph-captured launch
     const ProbDev P = probs[p];
     const RegState* st = P.st;
     if (st->done) return;

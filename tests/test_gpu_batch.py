@@ -86,7 +86,7 @@ def _batch_problems(g, ctx, sizes, seed0=5000):
     return out
 
 
-@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("flags", [0, 2, 4])
 def test_batch_equals_single(g, ctx, flags):
     _say("batch_vs_single", flags)
     sizes = [(2000, 30000), (7000, 60000), (15000, 20000), (300, 50000), (40000, 100000)]
@@ -125,7 +125,7 @@ def test_batch_statuses(g, ctx):
     pr, src, gm = _c1(g, ctx, n=2000)
     far = np.eye(4)
     far[:3, 3] = [30, 0, 0]
-    for flags in (0, 1, 2):
+    for flags in (0, 1, 2, 4):
         res = ctx.register_batch([(src, None, gm, np.eye(4)), (src, None, gm, far), (src, None, gm, np.eye(4))],
                                  g.params(max_it=10, flags=flags))
         assert [r.status for r in res] == [0, 3, 0]
@@ -139,3 +139,25 @@ def test_batch_arg_errors(g, ctx):
         ctx.register_batch([], g.params())
     with pytest.raises(g.GicpError):
         ctx.register_batch([(src, None, gm, np.eye(4))], g.params(r_max=-1.0))
+
+
+def test_graph_replays_match_launches(g, ctx):
+    """The graph-captured iterations replay the default launches bit for bit:
+    several calls per batch shape (cached graph, replayed with eager calls of
+    other shapes in between), each replay checked."""
+    _say("graph_replays")
+    sizes = [(2000, 30000), (7000, 60000), (15000, 20000), (300, 50000)]
+    probs = _batch_problems(g, ctx, sizes, seed0=7000)
+    kw = dict(max_it=20, conv_rot=1e-6, conv_trans=1e-6)
+    batches = [probs[:2], probs[1:], probs[:2], [probs[3]], probs[1:], probs[:2]]
+    for rnd, bp in enumerate(batches):
+        items = [(p["src"], None, p["map"], np.eye(4)) for p in bp]
+        ref = ctx.register_batch(items, g.params(**kw))
+        got = ctx.register_batch(items, g.params(flags=g.FLAG_GRAPH, **kw))
+        for a, b in zip(ref, got):
+            assert a.status == b.status == 0 and a.iters == b.iters, rnd
+            assert (a.pose == b.pose).all() and (a.H == b.H).all() and (a.b == b.b).all(), rnd
+    with pytest.raises(g.GicpError):
+        ctx.register_batch([(probs[0]["src"], None, probs[0]["map"], np.eye(4))], g.params(flags=64))
+    for p in probs:
+        p["map"].close()
