@@ -38,6 +38,10 @@ BYTES_PER_UNIT = {
     3: 232.0,  # solve: 29 FP64 partials per ... (negligible)
 }
 GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix sort, table)", 3: "k_gn_solve"}
+# Calibrated HBM bytes per unit from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on
+# this workload (profiles/hbm_traffic__c2_60k_vs_1M_pmc.md); valid for the
+# kernels as they were when the counters were taken.
+TRAFFIC_BYTES_PER_UNIT = {1: 529.0, 0: 77.4}
 
 
 def log(*a):
@@ -200,9 +204,17 @@ def main():
     # plain per-frame form (one gicp_register call per frame)
     time_frames(ctx, gmap, frames, seq, prm, warm, 1)
     t_plain, _, _, _ = time_frames(ctx, gmap, frames, seq, prm, order, 1)
+    log(f"per-frame form timed: {args.steps / t_plain:.1f} frames/s")
     # batched form (the headline): `batch` frames per call
     time_frames(ctx, gmap, frames, seq, prm, warm, args.batch)
     elapsed, poses, iters, statuses = time_frames(ctx, gmap, frames, seq, prm, order, args.batch)
+    log(f"batched form timed: {args.steps / elapsed:.1f} frames/s")
+    # the batched form with its iterations replayed from a HIP graph
+    prm_graph = g.params(k=20, eps=1e-3, r_max=r_max, max_it=max_it, conv_rot=conv, conv_trans=conv,
+                         reg_mode=g.REG_PLANE, cell_src=src_cell, flags=g.FLAG_GRAPH)
+    time_frames(ctx, gmap, frames, seq, prm_graph, warm, args.batch)
+    elapsed_graph, poses_graph, _, _ = time_frames(ctx, gmap, frames, seq, prm_graph, order, args.batch)
+    same = all(np.array_equal(poses_graph[i], poses[i]) for i in poses)
     # the same frames again with the library's kernel timing (HIP events around
     # every kernel group) for the per-kernel table and the roofline
     elapsed_ev, _, _, _ = time_frames(ctx, gmap, frames, seq, prm, order, args.batch, prof=True)
@@ -210,6 +222,7 @@ def main():
     ctx.profile(False)
     fps = args.steps / elapsed
     fps_plain = args.steps / t_plain
+    log(f"graph form {args.steps / elapsed_graph:.1f} frames/s (poses equal: {same})")
     log(f"timed {args.steps} frames: batched ({args.batch}/call) {fps:.1f} frames/s "
         f"({args.steps / elapsed_ev:.1f} with kernel events), per-frame {fps_plain:.1f} "
         f"frames/s; mean iterations {np.mean(iters):.2f}, statuses {sorted(set(statuses))}")
@@ -226,8 +239,11 @@ def main():
     dom = max((gid for gid in prof if prof[gid][0] > 0 and gid in (0, 1)), key=lambda gid: prof[gid][1])
     n, ms, units = prof[dom]
     achieved = BYTES_PER_UNIT[dom] * units / (ms * 1e-3) / 1e9
+    traffic = TRAFFIC_BYTES_PER_UNIT.get(dom)
     roofline = {"kernel": GROUP_NAMES[dom], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None if traffic is None else round(traffic * units / n),
+                "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                 "bytes_per_unit": BYTES_PER_UNIT[dom], "units_per_launch": units / n,
                 "avg_launch_us": 1e3 * ms / n}
 
@@ -277,6 +293,9 @@ def main():
                            "form": "one gicp_register call per frame"},
         "batched_over_per_frame": round(fps / fps_plain, 3),
         "value_with_kernel_events": round(args.steps / elapsed_ev, 3),
+        "graph_form": {"value": round(args.steps / elapsed_graph, 3), "unit": "frames/s",
+                       "form": "batched, Gauss-Newton iterations replayed from a HIP graph (GICP_FLAG_GRAPH)",
+                       "poses_equal_to_batched": bool(same)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pose_err_vs_oracle": err_vs_oracle,

@@ -115,12 +115,14 @@ KEYFRAME, MAPPING_ONLY = 1, 2
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Loads libgicp.so (built in-tree by ``build.py``).  Raises if it is missing:
-    there is no fallback implementation."""
+def load(path: str = ""):
+    """Loads libgicp.so (built in-tree by ``build.py``; $GICP_LIBRARY names
+    another build of the same library).  Raises if it is missing: there is
+    no fallback implementation."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("GICP_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"libgicp.so not built ({path}); run paper_2403_12550_amd/build.py")
     lib = C.CDLL(path)
