@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--map-size", type=int, default=1_000_000)
     ap.add_argument("--map-cell", type=float, default=0.03)
-    ap.add_argument("--cpu-frames", type=int, default=4, help="frames the CPU oracle baseline registers")
+    ap.add_argument("--cpu-frames", type=int, default=20, help="frames the CPU oracle baseline registers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--c4", action="store_true", help="also time the 64-problem batch workload")
     ap.add_argument("--no-frontend", action="store_true",

@@ -210,12 +210,14 @@ int gicp_register(gicp_ctx* ctx, const float* src, const float* src_covs, int64_
                   double pose[16], double H[36], double b[6], float* src_covs_out,
                   gicp_stats* stats, void* stream);
 
-/* Registers `nprob` independent problems in one persistent work-queue kernel
- * (same method and parameters as gicp_register; problems may differ in size
- * and map).  Work items are chunks of 256 source points of one problem at its
- * current pose; the last chunk of an iteration runs that problem's FP64 solve
- * and posts its next iteration, so problems advance independently and finish
- * at their own iteration counts.  Outputs (host): poses [nprob][16],
+/* Registers `nprob` independent problems in one call (same method and
+ * parameters as gicp_register; problems may differ in size and map).  Source
+ * covariances of all problems come from one segmented grid and one set of
+ * k-NN launches; each Gauss-Newton iteration is one linearisation launch over
+ * the 64-point work items of every unfinished problem and one solve
+ * workgroup per problem, so problems finish at their own iteration counts
+ * (params->flags selects the per-problem, work-queue or graph-replayed forms
+ * described above, with identical results).  Outputs (host): poses [nprob][16],
  * Hs [nprob][36], bs [nprob][6] (each nullable), stats [nprob] (nullable).
  * Source covariances are computed first for problems whose src_covs is NULL.
  * Synchronises the stream once.  Returns GICP_E_ARG for nprob outside

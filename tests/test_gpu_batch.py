@@ -161,3 +161,26 @@ def test_graph_replays_match_launches(g, ctx):
         ctx.register_batch([(probs[0]["src"], None, probs[0]["map"], np.eye(4))], g.params(flags=64))
     for p in probs:
         p["map"].close()
+
+
+def test_autotune_choices(g, ctx, tmp_path, monkeypatch):
+    """The autotuner times real library calls and picks a candidate; the
+    choice changes speed only (results stay exact for every candidate)."""
+    from paper_2403_12550_amd import autotune as at
+    monkeypatch.setattr(at, "CACHE", str(tmp_path / "tune.json"))
+    _say("autotune")
+    pr, src, gm = _c1(g, ctx, n=5000)
+    cell, rec = at.tune_source_cell(ctx, src, 20)
+    assert cell > 0 and rec["factor"] in at.SRC_FACTORS and len(rec["ms"]) == len(at.SRC_FACTORS)
+    # cached on the second call
+    cell2, rec2 = at.tune_source_cell(ctx, src, 20)
+    assert cell2 == cell and rec2 == rec
+    # every candidate gives the same covariances bit for bit
+    base = ctx.covariances(src, 20, cell=cell).cpu().numpy()
+    for f in at.SRC_FACTORS[:3]:
+        other = ctx.covariances(src, 20, cell=ctx.estimate_cell(src, 20) * f).cpu().numpy()
+        assert (other.view(np.uint32) == base.view(np.uint32)).all()
+    frames = [src] * 8
+    b, recb = at.tune_batch(ctx, gm, frames, [np.eye(4)] * 8, g.params(max_it=10), use_cache=False)
+    assert b in at.BATCHES and b <= 8
+    gm.close()
