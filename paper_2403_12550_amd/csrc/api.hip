@@ -72,7 +72,7 @@ struct gicp_ctx {
     int* d_err = nullptr;
     int* h_err = nullptr;
     GridBufs grid;
-    Buf covs, partials, kth, ssrc, sscov, nn_prev, overflow;
+    Buf covs, partials, kth, ssrc, sscov, nn_prev, nn_cache, overflow;
     RegState* d_state = nullptr;     // [state_cap]
     RegState* h_state = nullptr;     // pinned [state_cap]
     ProbDev* d_probs = nullptr;      // [state_cap]
@@ -363,7 +363,7 @@ int gicp_destroy(gicp_ctx* c) {
     (void)hipDeviceSynchronize();
     for (Buf* b : {&c->grid.keys_a, &c->grid.vals_a, &c->grid.keys_b, &c->grid.vals_b, &c->grid.scratch,
                    &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
-                   &c->nn_prev, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
+                   &c->nn_prev, &c->nn_cache, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
                    &c->mlp_lpair, &c->dep_pts, &c->dep_vox, &c->dep_flags, &c->dep_pos, &c->dep_scan, &c->dep_misc,
                    &c->ins_cov})
         release(*b);
@@ -593,6 +593,7 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
     float4* wsrc = nsorted ? ensure<float4>(c->ssrc, nsorted) : nullptr;
     float* wscov = nsorted ? ensure<float>(c->sscov, 6 * nsorted) : nullptr;
     int32_t* nnprev = ensure<int32_t>(c->nn_prev, ntot);
+    float4* nncache = ensure<float4>(c->nn_cache, ntot);
     // size the grid workspace for the largest source up front (a reallocation
     // between problems would synchronise the device)
     int64_t nmax = 0, run = 0;
@@ -711,7 +712,9 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         pd.ssrc = ssrc[p];
         pd.sscov = sscov[p];
         pd.nn_prev = nnprev;
+        pd.nn_cache = nncache;
         nnprev += P.n;
+        nncache += P.n;
         pd.n = P.n;
         pd.nchunks = (int32_t)((P.n + kChunk - 1) / kChunk);
         pd.part0 = (int32_t)chunks;

@@ -66,6 +66,18 @@ __device__ __forceinline__ double column_sum(const float* col, int n, int stride
 // split the same way, and after kMaxShell shells the whole map is scanned.
 // Returns the sorted position of the nearest mean within the gate, or -1, on
 // every lane of the group.
+//
+// With TRACK2 the search also bounds the second-nearest distance from below
+// (the second-best key seen, the lower bounds of every pruned cell and the
+// clearance of the scanned block) and returns in free_r a radius within
+// which q can move without changing its nearest mean: with d1 the nearest
+// and d2 that bound, |q' - q| < (d2 - d1) / 2 keeps every other mean farther
+// than the nearest one (margins cover the FP32 keys and coordinates);
+// free_r < 0 when there is no correspondence or no margin.
+__device__ __forceinline__ float key_of(uint64_t w) {
+    return w == ~0ull ? FLT_MAX : __uint_as_float((uint32_t)(w >> 32));
+}
+
 __device__ __forceinline__ void group_min(uint64_t& best, int32_t& pos) {
 #pragma unroll
     for (int o = 1; o < kGroup; o <<= 1) {
@@ -78,14 +90,39 @@ __device__ __forceinline__ void group_min(uint64_t& best, int32_t& pos) {
     }
 }
 
+// As group_min, also combining each lane's second-best key and pruned-cell bound.
+__device__ __forceinline__ void group_min2(uint64_t& best, int32_t& pos, float& second, float& minlb) {
+#pragma unroll
+    for (int o = 1; o < kGroup; o <<= 1) {
+        const uint64_t ob = __shfl_xor(best, o, 64);
+        const int32_t op = __shfl_xor(pos, o, 64);
+        const float os = __shfl_xor(second, o, 64);
+        const float om = __shfl_xor(minlb, o, 64);
+        second = fminf(second, os);
+        minlb = fminf(minlb, om);
+        if (ob < best) {
+            if (ob != best) second = fminf(second, key_of(best));
+            best = ob;
+            pos = op;
+        } else if (ob != best) {
+            second = fminf(second, key_of(ob));
+        }
+    }
+}
+
 // `hint` (a map position, or -1) is a candidate evaluated first, typically the
 // point's match of the previous iteration: with its key as the starting bound,
 // pruning skips nearly every cell, and the search stays exact.
-__device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz, int l, int32_t hint) {
+template <bool TRACK2>
+__device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz, int l, int32_t hint,
+                                           float* free_r = nullptr) {
     const GridView& g = m.g;
     const bool fin = finite3(qx, qy, qz);
     uint64_t best = ~0ull;
     int32_t pos = -1;
+    float second = FLT_MAX, minlb = FLT_MAX;
+    // every lane starts from the hint (equal words are merged once by the
+    // group reduction, and the lane owning the hint's cell skips it there)
     if (fin && hint >= 0 && hint < g.n) {
         const float4 p = g.spts[hint];
         best = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
@@ -94,17 +131,25 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
     const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, g.inv_h);
     const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
     auto scan = [&](int cx, int cy, int cz) {
-        const float bound =
-            fminf(best == ~0ull ? FLT_MAX : __uint_as_float((uint32_t)(best >> 32)), m.r_max2);
-        if (cell_pruned(cell_lower_bound2(qx, qy, qz, cx, cy, cz, g.h, slack), bound)) return;
+        const float bound = fminf(key_of(best), m.r_max2);
+        const float lb = cell_lower_bound2(qx, qy, qz, cx, cy, cz, g.h, slack);
+        if (cell_pruned(lb, bound)) {
+            if (TRACK2) minlb = fminf(minlb, lb);
+            return;
+        }
         uint32_t start = 0;
         const uint32_t cnt = cell_lookup(g.table, g.mask, cell_key(cx, cy, cz), start);
         for (uint32_t j = 0; j < cnt; ++j) {
-            const float4 p = g.spts[start + j];
+            const int32_t pj = (int32_t)(start + j);
+            if (TRACK2 && pj == pos) continue;   // the hint, already counted
+            const float4 p = g.spts[pj];
             const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
             if (v < best) {
+                if (TRACK2) second = fminf(second, key_of(best));
                 best = v;
-                pos = (int32_t)(start + j);
+                pos = pj;
+            } else if (TRACK2) {
+                second = fminf(second, key_of(v));
             }
         }
     };
@@ -115,34 +160,51 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             scan(c.x + dx, c.y + dy, c.z + dz);
         }
     }
-    group_min(best, pos);
-    if (!fin) return -1;
+    if (TRACK2) group_min2(best, pos, second, minlb);
+    else group_min(best, pos);
+    if (!fin) {
+        if (free_r) *free_r = -1.f;
+        return -1;
+    }
     const float r_gate = m.r_max * 1.000001f + 1e-6f;
     // shells needed for the gate to end the search (the full scan below is
     // reached only when r_max exceeds kMaxGateShells cells)
     const int max_shell = min(max(kMaxShell, (int)ceilf(r_gate * g.inv_h) + 1), kMaxGateShells);
+    float clr_end = FLT_MAX;   // every mean outside the scanned region is at least this far
     for (int R = 1;; ++R) {
         const float clr = block_clearance(qx, qy, qz, c, R, g.h);
         if (clr > 0.f) {
-            if (clr >= r_gate) break;
+            if (clr >= r_gate) {
+                clr_end = clr;
+                break;
+            }
             if (best != ~0ull) {
-                const float bk = __uint_as_float((uint32_t)(best >> 32));
-                if (bk < clr * clr * (1.f - 1e-6f)) break;
+                const float bk = key_of(best);
+                if (bk < clr * clr * (1.f - 1e-6f)) {
+                    clr_end = clr;
+                    break;
+                }
             }
         }
         if (R >= max_shell) {
             // full scan (exact by construction), split across the group
             best = ~0ull;
             pos = -1;
+            second = FLT_MAX;
+            minlb = FLT_MAX;
             for (int32_t j = l; j < g.n; j += kGroup) {
                 const float4 p = g.spts[j];
                 const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
                 if (v < best) {
+                    if (TRACK2) second = fminf(second, key_of(best));
                     best = v;
                     pos = j;
+                } else if (TRACK2) {
+                    second = fminf(second, key_of(v));
                 }
             }
-            group_min(best, pos);
+            if (TRACK2) group_min2(best, pos, second, minlb);
+            else group_min(best, pos);
             break;
         }
         const int S = R + 1;
@@ -154,11 +216,22 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                         if ((idx & (kGroup - 1)) == l) scan(c.x + dx, c.y + dy, c.z + dz);
                         ++idx;
                     }
-        group_min(best, pos);
+        if (TRACK2) group_min2(best, pos, second, minlb);
+        else group_min(best, pos);
     }
-    if (pos < 0) return -1;
-    const float bk = __uint_as_float((uint32_t)(best >> 32));
-    return (bk <= m.r_max2) ? pos : -1;
+    const float bk = key_of(best);
+    const int32_t res = (pos >= 0 && bk <= m.r_max2) ? pos : -1;
+    if (TRACK2 && free_r) {
+        float fr = -1.f;
+        if (res >= 0) {
+            const float k2 = fminf(fminf(second, minlb), clr_end * clr_end);
+            const float d1 = sqrtf(bk), d2 = sqrtf(k2);
+            const float mag = fmaxf(fmaxf(fabsf(qx), fabsf(qy)), fabsf(qz));
+            fr = 0.5f * (d2 * (1.f - 1e-5f) - d1 * (1.f + 1e-5f)) - 4e-6f * (1.f + mag);
+        }
+        *free_r = fr;
+    }
+    return res;
 }
 
 // Linearisation of source point i at the pose (R, t), evaluated by a group of
@@ -189,8 +262,28 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     const float qy = R[3] * x + R[4] * y + R[5] * z + t[1];
     const float qz = R[6] * x + R[7] * y + R[8] * z + t[2];
     const MapView& map = P.map;
-    const int32_t pos = nearest(map, qx, qy, qz, l, P.nn_prev[i]);
-    if (l == 0) P.nn_prev[i] = pos;
+    // the previous iteration's match stands while q stays within the radius
+    // its search certified (the nearest mean cannot have changed); otherwise
+    // search again
+    const int32_t hint = P.nn_prev[i];
+    bool reuse = false;
+    if (hint >= 0) {
+        const float4 cq = P.nn_cache[i];
+        const float ex = qx - cq.x, ey = qy - cq.y, ez = qz - cq.z;
+        reuse = sqrtf(ex * ex + ey * ey + ez * ez) < cq.w;
+    }
+    int32_t pos;
+    if (reuse) {
+        const float4 p = map.g.spts[hint];
+        pos = rank_key(qx, qy, qz, p.x, p.y, p.z) <= map.r_max2 ? hint : -1;
+    } else {
+        float free_r;
+        pos = nearest<true>(map, qx, qy, qz, l, hint, &free_r);
+        if (l == 0) {
+            P.nn_prev[i] = pos;
+            P.nn_cache[i] = make_float4(qx, qy, qz, free_r);
+        }
+    }
     if (pos < 0) return false;
     const float4 mu = map.g.spts[pos];
     const float4 ca = map.scov[2 * pos];
@@ -636,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_overlap(MapView m, const float* __re
     const float qx = T.R[0] * x + T.R[1] * y + T.R[2] * z + T.t[0];
     const float qy = T.R[3] * x + T.R[4] * y + T.R[5] * z + T.t[1];
     const float qz = T.R[6] * x + T.R[7] * y + T.R[8] * z + T.t[2];
-    const int32_t pos = nearest(m, qx, qy, qz, l, -1);
+    const int32_t pos = nearest<false>(m, qx, qy, qz, l, -1);
     if (l == 0) keep[i] = pos < 0 ? 1u : 0u;
 }
 

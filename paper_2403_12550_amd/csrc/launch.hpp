@@ -118,7 +118,8 @@ struct ProbDev {
     const float* scov;    // SoA [6][n]
     const float4* ssrc;   // nullable: the source in grid-cell order (x, y, z, original index)
     const float* sscov;   // with ssrc: the source covariances in that order, SoA [6][n]
-    int32_t* nn_prev;     // [n] map position matched by each point at the last iteration (-1: none)
+    int32_t* nn_prev;     // [n] map position matched by each point at its last search (-1: none)
+    float4* nn_cache;     // [n] query point of that search and the radius it certified
     int64_t n;
     int32_t nchunks;      // ceil(n / kChunk)
     int32_t part0;        // first partial / item slot of the problem
