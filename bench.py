@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed frames")
     ap.add_argument("--warmup", type=int, default=20, help="untimed frames before the timed ones")
-    ap.add_argument("--batch", type=int, default=20, help="frames per gicp_register_batch call")
+    ap.add_argument("--batch", type=int, default=50, help="frames per gicp_register_batch call")
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--map-size", type=int, default=1_000_000)
     ap.add_argument("--map-cell", type=float, default=0.03)
@@ -199,6 +199,9 @@ def main():
                    reg_mode=g.REG_PLANE, cell_src=src_cell)
     nf = args.frames
     warm = [i % nf for i in range(args.warmup)]
+    # the batched forms warm up on a whole batch, so that the timed calls find
+    # their workspaces sized
+    warm_batch = [i % nf for i in range(max(args.warmup, args.batch))]
     order = [(args.warmup + i) % nf for i in range(args.steps)]
 
     # plain per-frame form (one gicp_register call per frame)
@@ -206,13 +209,13 @@ def main():
     t_plain, _, _, _ = time_frames(ctx, gmap, frames, seq, prm, order, 1)
     log(f"per-frame form timed: {args.steps / t_plain:.1f} frames/s")
     # batched form (the headline): `batch` frames per call
-    time_frames(ctx, gmap, frames, seq, prm, warm, args.batch)
+    time_frames(ctx, gmap, frames, seq, prm, warm_batch, args.batch)
     elapsed, poses, iters, statuses = time_frames(ctx, gmap, frames, seq, prm, order, args.batch)
     log(f"batched form timed: {args.steps / elapsed:.1f} frames/s")
     # the batched form with its iterations replayed from a HIP graph
     prm_graph = g.params(k=20, eps=1e-3, r_max=r_max, max_it=max_it, conv_rot=conv, conv_trans=conv,
                          reg_mode=g.REG_PLANE, cell_src=src_cell, flags=g.FLAG_GRAPH)
-    time_frames(ctx, gmap, frames, seq, prm_graph, warm, args.batch)
+    time_frames(ctx, gmap, frames, seq, prm_graph, warm_batch, args.batch)
     elapsed_graph, poses_graph, _, _ = time_frames(ctx, gmap, frames, seq, prm_graph, order, args.batch)
     same = all(np.array_equal(poses_graph[i], poses[i]) for i in poses)
     # the same frames again with the library's kernel timing (HIP events around

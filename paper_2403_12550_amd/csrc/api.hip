@@ -211,6 +211,7 @@ GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const SegSet& S, int64_t total,
     gb.sorted_vals = vs;
     GridView g;
     g.spts = spts;
+    g.skeys = ks;
     g.table = table;
     g.mask = cap - 1;
     g.n = (int32_t)total;
@@ -522,6 +523,7 @@ namespace {
 MapView map_view(const gicp_map* map, const gicp_params* prm) {
     MapView mv;
     mv.g.spts = map->spts;
+    mv.g.skeys = map->keys;
     mv.g.table = map->table;
     mv.g.mask = map->mask;
     mv.g.n = (int32_t)map->m;

@@ -159,10 +159,19 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
                     }
                 }
             }
-            for (uint32_t i = 0; i < cnt; ++i) {
-                const float4 p = g.spts[start + i];
-                const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-                if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+            // the cell's points in groups of four loads issued together
+            for (uint32_t i0 = 0; i0 < cnt; i0 += 4) {
+                float4 pp[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < cnt) pp[u] = g.spts[start + i0 + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (i0 + u < cnt) {
+                        const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
+                        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(pp[u].w)));
+                    }
+                }
             }
         }
     }
@@ -415,7 +424,7 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, SegSet
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t s = (int64_t)blockIdx.x * (kT / kGroup) + threadIdx.x / kGroup;
     if (s >= g.n) return;   // uniform over each lane group
-    const int p = S.find(s);
+    const int p = S.of_key(g.skeys[s]);
     const Seg sg = S.get(p);
     const float4 q = g.spts[s];
     const float gate = kGateCells * sg.h;
@@ -452,7 +461,7 @@ __global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, Seg
     const int32_t* list = work + 2;
     for (int64_t e = blockIdx.x + (int64_t)gridDim.x * grp; e < count; e += (int64_t)gridDim.x * kG) {
         const int64_t s = list[e];
-        const int p = S.find(s);
+        const int p = S.of_key(g.skeys[s]);
         const Seg sg = S.get(p);
         const float4 q = g.spts[s];
         TopK<K> top;
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_cov_regularise(GridView g, SegSet S,
                                                            const float* __restrict__ raw) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
-    const Seg sg = S.get(S.find(s));
+    const Seg sg = S.get(S.of_key(g.skeys[s]));
     const float* r = raw + 6 * sg.off + (s - sg.off);
     Sym3 C;
     C.a00 = r[0]; C.a01 = r[sg.n]; C.a02 = r[2 * sg.n]; C.a11 = r[3 * sg.n]; C.a12 = r[4 * sg.n]; C.a22 = r[5 * sg.n];
@@ -568,7 +577,7 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov_overflow(GridView 
     const int32_t* list = work + 2 + g.n;
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
         const int64_t s = list[e];
-        const int p = S.find(s);
+        const int p = S.of_key(g.skeys[s]);
         const Seg sg = S.get(p);
         const float4 q = g.spts[s];
         TopK<K> top;

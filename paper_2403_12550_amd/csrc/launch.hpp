@@ -34,6 +34,8 @@ struct SegSet {
     int count;
 
     __device__ __forceinline__ Seg get(int p) const { return count == 1 ? one : many[p]; }
+    // cloud of grid-order position s: the top byte of its sorted cell key
+    __device__ __forceinline__ int of_key(uint32_t key) const { return count == 1 ? 0 : (int)(key >> 24); }
     // cloud holding concatenated (or grid-order) index i
     __device__ __forceinline__ int find(int64_t i) const {
         if (count == 1) return 0;
@@ -63,6 +65,7 @@ hipError_t launch_table_build(const uint32_t* skeys, const uint32_t* svals, int6
 // A built grid: cell-sorted points and the cell table.
 struct GridView {
     const float4* spts;   // [n] x, y, z, original index (bits)
+    const uint32_t* skeys;   // [n] sorted cell keys (cloud index in the top byte when segmented); may be null for maps
     const uint4* table;   // [mask+1] {key, start, count, -}
     uint32_t mask;
     int32_t n;
