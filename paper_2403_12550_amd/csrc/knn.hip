@@ -99,6 +99,8 @@ __device__ __forceinline__ void merge_lists(TopK<K>& top, int k, int l, uint64_t
     __builtin_amdgcn_wave_barrier();
 }
 
+constexpr int kShellBatch = 8;   // table slots loaded together per lane in a batched shell scan
+
 // Exact k-NN of q by a group of kGroup consecutive lanes (lane l; all hold
 // q).  Each lane fills its own top-k from every kGroup-th cell of the 27-cell
 // block (nearest cells first; a cell is skipped when its distance lower bound
@@ -111,7 +113,7 @@ __device__ __forceinline__ void merge_lists(TopK<K>& top, int k, int l, uint64_t
 template <int K>
 __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv_h, uint32_t prefix, float qx,
                                            float qy, float qz, int k, float gate2, float r_gate, TopK<K>& top, int l,
-                                           uint64_t* lists, int max_shell = kMaxShell) {
+                                           uint64_t* lists, int max_shell = kMaxShell, bool batched_shells = false) {
     top.init(k);
     const bool fin = finite3(qx, qy, qz);   // a non-finite query has no neighbour with a finite distance
     const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, inv_h);
@@ -191,12 +193,50 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
         // shell S = R + 1: the cells at Chebyshev distance S, every kGroup-th
         // one per lane (positions of the (2S+1)^3 cube, interior skipped)
         const int S = R + 1, W = 2 * S + 1;
-        for (int t = l; t < W * W * W; t += kGroup) {
-            const int dx = t % W - S, dy = (t / W) % W - S, dz = t / (W * W) - S;
-            if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
-            const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
-            if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-            scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+        if (!batched_shells) {
+            for (int t = l; t < W * W * W; t += kGroup) {
+                const int dx = t % W - S, dy = (t / W) % W - S, dz = t / (W * W) - S;
+                if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
+                const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
+                if (cell_pruned(lb, prune_bound(top, gate2))) continue;
+                scan_cell<K>(g, prefix | cell_key(c.x + dx, c.y + dy, c.z + dz), qx, qy, qz, gate2, top);
+            }
+        } else {
+            // up to kShellBatch unpruned cells of the lane at a time: their
+            // table slots are loaded together, then the cells are scanned
+            int t = l;
+            while (t < W * W * W) {
+                uint4 ent[kShellBatch];
+                uint32_t key[kShellBatch];
+#pragma unroll
+                for (int b = 0; b < kShellBatch; ++b) {
+                    key[b] = kEmptyKey;
+                    while (t < W * W * W) {
+                        const int dx = t % W - S, dy = (t / W) % W - S, dz = t / (W * W) - S;
+                        t += kGroup;
+                        if (max(max(abs(dx), abs(dy)), abs(dz)) != S) continue;
+                        const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
+                        if (cell_pruned(lb, prune_bound(top, gate2))) continue;
+                        key[b] = prefix | cell_key(c.x + dx, c.y + dy, c.z + dz);
+                        ent[b] = g.table[hash_slot(key[b], g.mask)];
+                        break;
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < kShellBatch; ++b) {
+                    if (key[b] == kEmptyKey) continue;
+                    uint32_t start = ent[b].y, cnt = ent[b].z;
+                    if (ent[b].x != key[b]) {
+                        cnt = 0;
+                        if (ent[b].x != kEmptyKey) cnt = cell_lookup(g.table, g.mask, key[b], start);
+                    }
+                    for (uint32_t i = 0; i < cnt; ++i) {
+                        const float4 p = g.spts[start + i];
+                        const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
+                        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+                    }
+                }
+            }
         }
         merge_lists<K>(top, k, l, lists);
     }
@@ -468,7 +508,7 @@ __global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, Seg
         const float gate = kRetryGateCells * sg.h;
         const float gate2 = gate * gate;
         if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, gate2,
-                           gate * 1.000001f + 1e-6f, top, l, s_lists[grp]) ||
+                           gate * 1.000001f + 1e-6f, top, l, s_lists[grp], kMaxShell, true) ||
             top.v[K - 1] == ~0ull) {
             if (l == 0) push_work(work, g.n, 1, s);
             continue;
@@ -671,7 +711,7 @@ __global__ void k_map_covs(const uint32_t* __restrict__ svals, int64_t m, const 
     scov[2 * i + 1] = make_float4(o[4], o[5], 0.f, 0.f);
 }
 
-constexpr int kOverflowBlocks = 256;
+constexpr int kOverflowBlocks = 2048;
 
 constexpr int kRetryBlocks = 1024;
 

@@ -49,7 +49,8 @@ struct SegSet {
     }
 };
 
-constexpr int kMaxSegments = 256;
+// at most 255 clouds per segmented grid: cloud 255 could form the key 0xFFFFFFFF, the empty-slot marker
+constexpr int kMaxSegments = 255;
 
 // Cell keys of the concatenated clouds (cloud index << 24 | cell key) with
 // their concatenated indices as values.

@@ -184,3 +184,23 @@ def test_autotune_choices(g, ctx, tmp_path, monkeypatch):
     b, recb = at.tune_batch(ctx, gm, frames, [np.eye(4)] * 8, g.params(max_it=10), use_cache=False)
     assert b in at.BATCHES and b <= 8
     gm.close()
+
+
+def test_batch_more_than_one_segment_group(g, ctx):
+    """More sources than one segmented grid holds (255): the call splits them
+    into groups; every result equals the single registration."""
+    _say("batch_300")
+    pr, src, gm = _c1(g, ctx, n=1500)
+    rng = np.random.default_rng(11)
+    inits = []
+    for _ in range(300):
+        T = np.eye(4)
+        T[:3, 3] = rng.normal(0, 0.01, 3)
+        inits.append(T)
+    prm = g.params(max_it=8)
+    batch = ctx.register_batch([(src, None, gm, T) for T in inits], prm)
+    for j in (0, 254, 255, 299):
+        rs = ctx.register(src, gm, inits[j], prm)
+        assert batch[j].status == rs.status == 0
+        assert (batch[j].pose == rs.pose).all() and (batch[j].H == rs.H).all(), j
+    gm.close()
