@@ -41,7 +41,7 @@ GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix 
 # Calibrated HBM bytes per unit from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on
 # this workload (profiles/hbm_traffic__c2_60k_vs_1M_pmc.md); valid for the
 # kernels as they were when the counters were taken.
-TRAFFIC_BYTES_PER_UNIT = {1: 529.0, 0: 77.4}
+TRAFFIC_BYTES_PER_UNIT = {1: 490.2, 0: 66.5}
 
 
 def log(*a):

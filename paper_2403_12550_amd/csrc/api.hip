@@ -583,15 +583,11 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
                    float* const* covs_out, double* poses, double* Hs, double* bs, gicp_stats* stats, hipStream_t s) {
     // 1. source covariances where missing; such problems are then linearised
     // in their grid-cell order (sorted copies of the points and covariances)
-    int64_t need = 0, nsorted = 0, ntot = 0;
+    int64_t nsorted = 0, ntot = 0;
     for (int p = 0; p < nprob; ++p) {
         ntot += probs[p].n;
-        if (!probs[p].src_covs) {
-            nsorted += probs[p].n;
-            if (!(covs_out && covs_out[p])) need += 6 * probs[p].n;
-        }
+        if (!probs[p].src_covs) nsorted += probs[p].n;
     }
-    float* wcov = need ? ensure<float>(c->covs, need) : nullptr;
     float4* wsrc = nsorted ? ensure<float4>(c->ssrc, nsorted) : nullptr;
     float* wscov = nsorted ? ensure<float>(c->sscov, 6 * nsorted) : nullptr;
     int32_t* nnprev = ensure<int32_t>(c->nn_prev, ntot);
@@ -651,12 +647,9 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         for (size_t q = g0; q < g1; ++q) {
             const int p = todo[q];
             const gicp_problem& P = probs[p];
-            float* out = covs_out ? covs_out[p] : nullptr;
-            float* dst = out;
-            if (!dst) {
-                dst = wcov;
-                wcov += 6 * P.n;
-            }
+            // the registration reads the cell-order copy; the caller's order is
+            // written only when the caller asked for the covariances
+            float* dst = covs_out ? covs_out[p] : nullptr;
             const float h = cells[p];
             Seg& sg = c->h_segs[q - g0];
             sg.xyz = P.src;

@@ -387,8 +387,10 @@ __device__ __forceinline__ Sym3 raw_from_topk(const TopK<K>& top, int k, const f
 
 __device__ __forceinline__ void store_cov(const float out[6], float* __restrict__ covs, float* __restrict__ covs_sorted,
                                           int64_t cstride, uint32_t orig, int32_t s) {
+    if (covs) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) covs[(int64_t)c * cstride + orig] = out[c];
+        for (int c = 0; c < 6; ++c) covs[(int64_t)c * cstride + orig] = out[c];
+    }
     if (covs_sorted) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) covs_sorted[(int64_t)c * cstride + s] = out[c];
