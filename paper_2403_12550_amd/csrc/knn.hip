@@ -134,45 +134,61 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
                 ent[q] = g.table[hash_slot(key, g.mask)];
             }
         }
+        // resolve them to (start, count); cells beyond the gate count 0
+        uint32_t st[kPer], ct[kPer];
+        uint32_t total = 0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int j = l + kGroup * q;
-            if (j >= 27) continue;
-            int dx, dy, dz;
-            block_offset(j, dx, dy, dz);
-            const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
-            if (cell_pruned(lb, prune_bound(top, gate2))) continue;
-            const uint32_t key = prefix | cell_key(c.x + dx, c.y + dy, c.z + dz);
-            uint32_t start = ent[q].y, cnt = ent[q].z;
-            if (ent[q].x != key) {
-                // empty slot: no such cell; another key: probe on from the next slot
-                cnt = 0;
-                if (ent[q].x != kEmptyKey) {
-                    uint32_t sl = (hash_slot(key, g.mask) + 1u) & g.mask;
-                    while (true) {
-                        const uint4 e = g.table[sl];
-                        if (e.x == key) {
-                            start = e.y;
-                            cnt = e.z;
-                            break;
-                        }
-                        if (e.x == kEmptyKey) break;
-                        sl = (sl + 1u) & g.mask;
+            st[q] = 0;
+            ct[q] = 0;
+            if (j < 27) {
+                int dx, dy, dz;
+                block_offset(j, dx, dy, dz);
+                const float lb = cell_lower_bound2(qx, qy, qz, c.x + dx, c.y + dy, c.z + dz, h, slack);
+                if (!cell_pruned(lb, gate2)) {
+                    const uint32_t key = prefix | cell_key(c.x + dx, c.y + dy, c.z + dz);
+                    if (ent[q].x == key) {
+                        st[q] = ent[q].y;
+                        ct[q] = ent[q].z;
+                    } else if (ent[q].x != kEmptyKey) {
+                        // another key in the slot: probe on
+                        ct[q] = cell_lookup(g.table, g.mask, key, st[q]);
                     }
                 }
             }
-            // the cell's points in groups of four loads issued together
-            for (uint32_t i0 = 0; i0 < cnt; i0 += 4) {
-                float4 pp[4];
+            total += ct[q];
+        }
+        // one flat loop over all of the lane's candidates: the trip count is
+        // the lane's candidate total, so the lanes of a wavefront stay close
+        // in work (a loop per cell would cost every wavefront the sum over
+        // cells of the largest count among its lanes); loads four at a time
+        int q = 0;
+        uint32_t cs = 0, cl = 0;
+        for (uint32_t j0 = 0; j0 < total; j0 += 4) {
+            float4 pp[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (i0 + u < cnt) pp[u] = g.spts[start + i0 + u];
+            for (int u = 0; u < 4; ++u) {
+                if (j0 + u < total) {
+                    while (cl == 0 && q < kPer) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (i0 + u < cnt) {
-                        const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
-                        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(pp[u].w)));
+                        for (int t = 0; t < kPer; ++t)
+                            if (q == t) {
+                                cs = st[t];
+                                cl = ct[t];
+                            }
+                        ++q;
                     }
+                    pp[u] = g.spts[cs];
+                    ++cs;
+                    --cl;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (j0 + u < total) {
+                    const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
+                    if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(pp[u].w)));
                 }
             }
         }
