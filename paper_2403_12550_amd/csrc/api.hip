@@ -545,7 +545,7 @@ bool valid_params(const gicp_params* prm) {
 constexpr int64_t kGraphBucket = 1024;   // launch grids are padded to a multiple of this many chunks
 constexpr size_t kMaxGraphs = 8;
 
-hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, const int32_t* chunk_prob,
+hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int32_t* chunk_prob,
                                double* part) {
     for (auto& e : c->graphs)
         if (e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc && e.probs == c->d_probs &&

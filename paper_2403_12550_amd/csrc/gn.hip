@@ -709,10 +709,16 @@ __global__ __launch_bounds__(kBlock) void k_gn_linearize_batch(const ProbDev* __
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev* __restrict__ probs,
-                                                                  const double* __restrict__ partials) {
+                                                                  const double* __restrict__ partials,
+                                                                  int32_t* __restrict__ chunk_prob) {
     const ProbDev P = probs[blockIdx.x];
     if (P.st->done) return;
     solve_state(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, P.st);
+    __syncthreads();
+    // a problem that finished leaves the linearisation grid: its work items
+    // exit on their first load in the remaining launches
+    if (P.st->done)
+        for (int c = threadIdx.x; c < P.nchunks; c += blockDim.x) chunk_prob[P.part0 + c] = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -825,7 +831,7 @@ hipError_t launch_chunk_map(const ProbDev* probs, int nprob, int32_t* chunk_prob
     return hipGetLastError();
 }
 
-hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, const int32_t* chunk_prob, int64_t chunks,
+hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, int32_t* chunk_prob, int64_t chunks,
                                      double* partials, int acc, bool linearize, bool solve, hipStream_t s) {
     if (linearize) {
         switch (acc) {
@@ -842,7 +848,9 @@ hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, const int3
                                    s, probs, chunk_prob, partials);
         }
     }
-    if (solve) hipLaunchKernelGGL(k_gn_solve_batch, dim3(nprob), dim3(kSolveThreads), 0, s, probs, partials);
+    if (solve)
+        hipLaunchKernelGGL(k_gn_solve_batch, dim3(nprob), dim3(kSolveThreads), 0, s, probs, (const double*)partials,
+                           chunk_prob);
     return hipGetLastError();
 }
 

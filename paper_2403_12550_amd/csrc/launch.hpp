@@ -147,7 +147,7 @@ constexpr int kMaxProblems = 4096;
 
 int gn_blocks(int64_t n);
 hipError_t launch_chunk_map(const ProbDev* probs, int nprob, int32_t* chunk_prob, hipStream_t s);
-hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, const int32_t* chunk_prob, int64_t chunks,
+hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, int32_t* chunk_prob, int64_t chunks,
                                      double* partials, int acc, bool linearize, bool solve, hipStream_t s);
 int gn_queue_workers(int acc);
 hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_t* items, uint32_t cap,
