@@ -223,10 +223,15 @@ def main():
     elapsed_ev, _, _, _ = time_frames(ctx, gmap, frames, seq, prm, order, args.batch, prof=True)
     prof = {gid: ctx.profile_read(gid) for gid in range(4)}
     ctx.profile(False)
-    fps = args.steps / elapsed
+    fps_launch = args.steps / elapsed
+    fps_graph = args.steps / elapsed_graph
+    # the headline is the graph-replayed batched form (same kernels and, as
+    # checked above, the same poses as the batched launches)
+    fps = fps_graph if same else fps_launch
+    elapsed_value = elapsed_graph if same else elapsed
     fps_plain = args.steps / t_plain
     log(f"graph form {args.steps / elapsed_graph:.1f} frames/s (poses equal: {same})")
-    log(f"timed {args.steps} frames: batched ({args.batch}/call) {fps:.1f} frames/s "
+    log(f"timed {args.steps} frames: batched ({args.batch}/call) {fps_launch:.1f} frames/s "
         f"({args.steps / elapsed_ev:.1f} with kernel events), per-frame {fps_plain:.1f} "
         f"frames/s; mean iterations {np.mean(iters):.2f}, statuses {sorted(set(statuses))}")
 
@@ -279,7 +284,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "ms_per_step": round(1e3 * elapsed_value / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -289,16 +294,17 @@ def main():
                                f"(mean {npts.mean():.0f} pts) vs a {args.map_size}-Gaussian map, "
                                f"{nf}-frame trajectory, k=20, plane eps=1e-3, r_max=0.1 m, <=20 GN it",
                    "frames": nf, "map_gaussians": args.map_size, "mean_points": float(npts.mean()),
-                   "form": f"batched: {args.batch} frames per gicp_register_batch call; a step is one frame",
+                   "form": f"batched: {args.batch} frames per gicp_register_batch call, Gauss-Newton iterations "
+                           "replayed from a HIP graph (GICP_FLAG_GRAPH); a step is one frame",
                    "init": "constant-velocity prediction from the previous two ground-truth poses"},
         "per_frame_form": {"value": round(fps_plain, 3), "unit": "frames/s",
                            "ms_per_frame": round(1e3 * t_plain / args.steps, 4),
                            "form": "one gicp_register call per frame"},
         "batched_over_per_frame": round(fps / fps_plain, 3),
-        "value_with_kernel_events": round(args.steps / elapsed_ev, 3),
-        "graph_form": {"value": round(args.steps / elapsed_graph, 3), "unit": "frames/s",
-                       "form": "batched, Gauss-Newton iterations replayed from a HIP graph (GICP_FLAG_GRAPH)",
-                       "poses_equal_to_batched": bool(same)},
+        "batched_launch_form": {"value": round(fps_launch, 3), "unit": "frames/s",
+                                "form": "batched, one launch per kernel and iteration",
+                                "graph_poses_equal": bool(same),
+                                "value_with_kernel_events": round(args.steps / elapsed_ev, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pose_err_vs_oracle": err_vs_oracle,
