@@ -158,6 +158,13 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             int dx, dy, dz;
             block_offset(j, dx, dy, dz);
             scan(c.x + dx, c.y + dy, c.z + dz);
+            // without a hint, the lanes share their best after the nearest
+            // four cells, so that every lane prunes the rest with the group's
+            // bound (a hint already gives every lane a tight bound)
+            if (j == l && hint < 0) {
+                if (TRACK2) group_min2(best, pos, second, minlb);
+                else group_min(best, pos);
+            }
         }
     }
     if (TRACK2) group_min2(best, pos, second, minlb);
