@@ -83,6 +83,9 @@ struct gicp_ctx {
     int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
     int h_kth_cap = 0;   // clouds the pinned estimate buffer holds
+    KthJob* h_jobs = nullptr;   // pinned descriptors of the estimate launch
+    int h_jobs_cap = 0;
+    Buf kth_jobs;
     Seg* h_segs = nullptr;           // pinned [kMaxSegments]
     Buf segs;
     // warm-start network workspaces
@@ -254,13 +257,24 @@ void estimate_cells(gicp_ctx* ctx, int count, const float* const* xyz, const int
         check(hipHostMalloc(&ctx->h_kth, (size_t)count * kEstimateSamples * sizeof(float)));
         ctx->h_kth_cap = count;
     }
+    // one launch for every cloud (the job descriptors go through pinned memory)
+    if (ctx->h_jobs_cap < count) {
+        if (ctx->h_jobs) check(hipHostFree(ctx->h_jobs));
+        ctx->h_jobs = nullptr;
+        ctx->h_jobs_cap = 0;
+        check(hipHostMalloc(&ctx->h_jobs, (size_t)count * sizeof(KthJob)));
+        ctx->h_jobs_cap = count;
+    }
     std::vector<int> ns(count);
     for (int i = 0; i < count; ++i) {
         ns[i] = (int)std::min<int64_t>(kEstimateSamples, n[i]);
         const int64_t step = std::max<int64_t>(1, n[i] / kEstimateScan);
         const int j = std::max(1, (int)std::lround((double)std::min<int64_t>(k, n[i]) / (double)step));
-        check(launch_kth_distance(xyz[i], n[i], j, ns[i], step, d + (int64_t)i * kEstimateSamples, s));
+        ctx->h_jobs[i] = KthJob{xyz[i], n[i], step, j, ns[i]};
     }
+    KthJob* djobs = ensure<KthJob>(ctx->kth_jobs, count);
+    check(hipMemcpyAsync(djobs, ctx->h_jobs, count * sizeof(KthJob), hipMemcpyHostToDevice, s));
+    check(launch_kth_distance(djobs, count, kEstimateSamples, d, s));
     check(hipMemcpyAsync(ctx->h_kth, d, (size_t)count * kEstimateSamples * sizeof(float), hipMemcpyDeviceToHost, s));
     check(hipStreamSynchronize(s));
     for (int i = 0; i < count; ++i) {
@@ -366,11 +380,12 @@ int gicp_destroy(gicp_ctx* c) {
                    &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
                    &c->nn_prev, &c->nn_cache, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
                    &c->mlp_lpair, &c->dep_pts, &c->dep_vox, &c->dep_flags, &c->dep_pos, &c->dep_scan, &c->dep_misc,
-                   &c->ins_cov})
+                   &c->ins_cov, &c->kth_jobs})
         release(*b);
     for (auto& ge : c->graphs) (void)hipGraphExecDestroy(ge.exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->h_pairs) (void)hipHostFree(c->h_pairs);
+    if (c->h_jobs) (void)hipHostFree(c->h_jobs);
     if (c->pairs_ev) (void)hipEventDestroy(c->pairs_ev);
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->d_state) (void)hipFree(c->d_state);

@@ -669,9 +669,16 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_query_overflow(GridVie
 // held more than 8 of the j smallest; used only to size grid cells).
 constexpr int kKthWaves = 4;
 
-__global__ __launch_bounds__(64 * kKthWaves) void k_kth_distance(const float* __restrict__ xyz, int64_t n, int j,
-                                                                 int ns, int64_t step, float* __restrict__ out) {
-    const int sample = blockIdx.x * kKthWaves + threadIdx.x / 64;
+__global__ __launch_bounds__(64 * kKthWaves) void k_kth_distance(const KthJob* __restrict__ jobs, int samples,
+                                                                 float* __restrict__ out_all) {
+    // block -> (job, group of kKthWaves samples); one wavefront per sample
+    const int per_job = (samples + kKthWaves - 1) / kKthWaves;
+    const KthJob J = jobs[blockIdx.x / per_job];
+    const float* __restrict__ xyz = J.xyz;
+    const int64_t n = J.n, step = J.step;
+    const int j = J.j, ns = J.ns;
+    float* __restrict__ out = out_all + (int64_t)(blockIdx.x / per_job) * samples;
+    const int sample = (blockIdx.x % per_job) * kKthWaves + threadIdx.x / 64;
     if (sample >= ns) return;   // uniform over the wavefront
     const int lane = threadIdx.x % 64;
     const int64_t qi = (int64_t)sample * n / ns;
@@ -787,9 +794,9 @@ hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q,
     return knn_query_t<64>(g, h, q, nq, k, gate2, r_gate, idx, d2, overflow, s);
 }
 
-hipError_t launch_kth_distance(const float* xyz, int64_t n, int j, int ns, int64_t step, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_kth_distance, dim3((ns + kKthWaves - 1) / kKthWaves), dim3(64 * kKthWaves), 0, s, xyz, n, j,
-                       ns, step, out);
+hipError_t launch_kth_distance(const KthJob* jobs, int njobs, int samples, float* out, hipStream_t s) {
+    const int per_job = (samples + kKthWaves - 1) / kKthWaves;
+    hipLaunchKernelGGL(k_kth_distance, dim3(njobs * per_job), dim3(64 * kKthWaves), 0, s, jobs, samples, out);
     return hipGetLastError();
 }
 

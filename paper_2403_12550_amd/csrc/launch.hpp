@@ -85,9 +85,14 @@ constexpr int64_t knn_cov_work_ints(int64_t total) { return 2 + 2 * total; }
 // row-major [nq][k]; overflow [1 + nq].
 hipError_t launch_knn_query(const GridView& g, const Seg& cloud, const float* q, int64_t nq, int k, float r_max,
                             int32_t* idx, float* d2, int32_t* overflow, hipStream_t s);
-// j-th neighbour distance of `ns` evenly strided samples among every
-// step-th point, by brute force.
-hipError_t launch_kth_distance(const float* xyz, int64_t n, int j, int ns, int64_t step, float* out, hipStream_t s);
+struct KthJob {
+    const float* xyz;   // SoA [3][n]
+    int64_t n, step;    // cloud size; only every step-th point is scanned
+    int j, ns;          // neighbour rank; number of strided samples (<= samples)
+};
+// For every job, the j-th neighbour distance of ns strided samples, into
+// out[job * samples + sample]; jobs is a device array of njobs entries.
+hipError_t launch_kth_distance(const KthJob* jobs, int njobs, int samples, float* out, hipStream_t s);
 // Map Gaussians: regularise covariances and store them in cell order (2 x float4 each).
 hipError_t launch_map_covs(const uint32_t* svals, int64_t m, const float* covs, int64_t stride, int mode,
                            float eps, float4* scov, int* err, hipStream_t s);
