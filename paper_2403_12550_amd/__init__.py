@@ -44,6 +44,15 @@ def params(**kw) -> Params:
     return p
 
 
+# numpy views of the batched call's C structs (same field order, sizes and
+# alignment as gicp_problem and gicp_stats), filled column by column
+_PROBLEM_DT = np.dtype([("src", np.uint64), ("src_covs", np.uint64), ("n", np.int64), ("map", np.uint64),
+                        ("init_pose", np.float64, (16,))])
+_STATS_DT = np.dtype([("iters", np.int32), ("n_inliers", np.int32), ("cost", np.float64), ("converged", np.int32),
+                      ("status", np.int32), ("hip_error", np.int32), ("reserved", np.int32)])
+assert _PROBLEM_DT.itemsize == C.sizeof(Problem) and _STATS_DT.itemsize == C.sizeof(Stats)
+
+
 def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
@@ -258,24 +267,26 @@ class Context:
         Returns a list of RegisterResult (one per problem)."""
         prm = prm or params()
         k = len(problems)
-        arr = (Problem * k)()
-        for i, (src, scov, gmap, init) in enumerate(problems):
+        arr = np.zeros(k, _PROBLEM_DT)
+        srcs, scovs, maps, inits = zip(*problems) if k else ((), (), (), ())
+        for src, scov in zip(srcs, scovs):
             _check_f32_cuda(src, 3, "src")
             if scov is not None:
                 _check_f32_cuda(scov, 6, "src_covs")
-            arr[i].src = _ptr(src)
-            arr[i].src_covs = _ptr(scov)
-            arr[i].n = src.shape[1]
-            arr[i].map = gmap.handle
-            arr[i].init_pose[:] = [float(v) for v in np.asarray(init, np.float64).reshape(16)]
-        poses = np.zeros((k, 16))
-        Hs = np.zeros((k, 36))
+        arr["src"] = [t.data_ptr() for t in srcs]
+        arr["src_covs"] = [0 if t is None else t.data_ptr() for t in scovs]
+        arr["n"] = [t.shape[1] for t in srcs]
+        arr["map"] = [m.handle.value or 0 for m in maps]
+        if k:
+            arr["init_pose"] = np.asarray(inits, np.float64).reshape(k, 16)
+        poses = np.zeros((k, 4, 4))
+        Hs = np.zeros((k, 6, 6))
         bs = np.zeros((k, 6))
-        stats = (Stats * k)()
-        st = lib().gicp_register_batch(self.handle, k, arr, C.byref(prm), poses.ctypes.data, Hs.ctypes.data,
-                                       bs.ctypes.data, stats, _stream())
+        stats = np.zeros(k, _STATS_DT)
+        st = lib().gicp_register_batch(self.handle, k, C.cast(arr.ctypes.data, C.POINTER(Problem)), C.byref(prm),
+                                       poses.ctypes.data, Hs.ctypes.data, bs.ctypes.data,
+                                       C.cast(stats.ctypes.data, C.POINTER(Stats)), _stream())
         if st in (_abi.GICP_E_ARG, _abi.GICP_E_HIP, _abi.GICP_E_OOM):
             raise GicpError(st, "gicp_register_batch")
-        return [RegisterResult(poses[i].reshape(4, 4), Hs[i].reshape(6, 6), bs[i], stats[i].iters,
-                               stats[i].n_inliers, stats[i].cost, bool(stats[i].converged), stats[i].status)
-                for i in range(k)]
+        return [RegisterResult(poses[i], Hs[i], bs[i], it, ni, cost, bool(cv), status)
+                for i, (it, ni, cost, cv, status, _, _) in enumerate(stats.tolist())]

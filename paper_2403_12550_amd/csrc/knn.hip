@@ -5,7 +5,7 @@
 // A group of four consecutive lanes serves one query: the lanes split the
 // cells of the 27-cell block, each keeps its own best candidates in registers
 // as 64-bit (FP32 key, original index) words, sorted, inserted with an
-// unrolled compare-exchange chain, and the four lists are merged through LDS.
+// unrolled min/max sweep, and the four lists are merged through LDS.
 // Queries of the self k-NN are the cell-sorted points themselves, so the
 // groups of a wavefront visit the same cells and the candidate reads are
 // served by the vector L1/L2.  After the 27-cell block the group proves
@@ -21,26 +21,47 @@ namespace gicp {
 
 namespace {
 
-// Sorted list of the best candidates as 64-bit (FP32 key, original index)
-// words.  For a runtime k < K the first K - k slots hold zero words, which sort
-// before every candidate and never move, so the k best always occupy slots
-// [K - k, K) and the k-th best is the last slot (a static register index).
+// Candidate words: (FP32 key bits + 2^20) << 32 | original index.  Unsigned
+// integer order is the (key, index) order, and the offset makes every word the
+// bit pattern of a positive normal double (exponent field 0x001 .. 0x7F9 for
+// keys from +0 to +inf), whose floating-point order is the same; the sorted
+// insertion below runs on v_min_f64 / v_max_f64.  The empty slot is +inf,
+// above every word.
+constexpr uint32_t kWordBias = 1u << 20;
+constexpr uint64_t kEmptyWord = 0x7FF0000000000000ull;
+
+__device__ __forceinline__ uint64_t word(float key, uint32_t idx) {
+    return ((uint64_t)(__float_as_uint(key) + kWordBias) << 32) | (uint64_t)idx;
+}
+
+__device__ __forceinline__ float word_key(uint64_t w) { return __uint_as_float((uint32_t)(w >> 32) - kWordBias); }
+
+// Sorted list of the best candidates as words.  For a runtime k < K the first
+// K - k slots hold zero words (+0.0), which sort before every candidate and
+// never move, so the k best always occupy slots [K - k, K) and the k-th best
+// is the last slot (a static register index).
 template <int K>
 struct TopK {
     uint64_t v[K];
     __device__ __forceinline__ void init(int k) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) v[j] = (j < K - k) ? 0ull : ~0ull;
+        for (int j = 0; j < K; ++j) v[j] = (j < K - k) ? 0ull : kEmptyWord;
     }
+    // One sweep from the front: slot j keeps min(v[j], t) and max(v[j], t)
+    // moves on, which places x and drops the largest word, two instructions
+    // per slot.  The min and max are written as v_min_f64 / v_max_f64 on the
+    // raw registers: as doubles, the words (no NaN, no denormal) compare
+    // exactly like the integers, and the compiler's own fmin / fmax would
+    // first quieten every operand.
     __device__ __forceinline__ void insert(uint64_t x) {
         if (x >= v[K - 1]) return;
-        v[K - 1] = x;
+        uint64_t t = x;
 #pragma unroll
-        for (int j = K - 1; j > 0; --j) {
-            const uint64_t a = v[j - 1], b = v[j];
-            const bool sw = b < a;
-            v[j - 1] = sw ? b : a;
-            v[j] = sw ? a : b;
+        for (int j = 0; j < K; ++j) {
+            uint64_t hi;
+            asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(v[j]), "v"(t));
+            asm("v_min_f64 %0, %0, %1" : "+v"(v[j]) : "v"(t));
+            t = hi;
         }
     }
 };
@@ -54,7 +75,7 @@ __device__ __forceinline__ void scan_cell(const GridView& g, uint32_t key, float
     for (uint32_t j = 0; j < cnt; ++j) {
         const float4 p = g.spts[start + j];
         const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+        if (d2 <= gate2) top.insert(word(d2, __float_as_uint(p.w)));
     }
 }
 
@@ -63,7 +84,7 @@ __device__ __forceinline__ void scan_cell(const GridView& g, uint32_t key, float
 template <int K>
 __device__ __forceinline__ float prune_bound(const TopK<K>& top, float gate2) {
     const uint64_t w = top.v[K - 1];
-    const float kth = (w == ~0ull) ? FLT_MAX : __uint_as_float((uint32_t)(w >> 32));
+    const float kth = (w == kEmptyWord) ? FLT_MAX : word_key(w);
     return fminf(kth, gate2);
 }
 
@@ -82,10 +103,10 @@ __device__ __forceinline__ void merge_lists(TopK<K>& top, int k, int l, uint64_t
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j < K - k) continue;   // dummy slots keep their zero words
-        const uint64_t a0 = h0 < K ? lists[0 * K + h0] : ~0ull;
-        const uint64_t a1 = h1 < K ? lists[1 * K + h1] : ~0ull;
-        const uint64_t a2 = h2 < K ? lists[2 * K + h2] : ~0ull;
-        const uint64_t a3 = h3 < K ? lists[3 * K + h3] : ~0ull;
+        const uint64_t a0 = h0 < K ? lists[0 * K + h0] : kEmptyWord;
+        const uint64_t a1 = h1 < K ? lists[1 * K + h1] : kEmptyWord;
+        const uint64_t a2 = h2 < K ? lists[2 * K + h2] : kEmptyWord;
+        const uint64_t a3 = h3 < K ? lists[3 * K + h3] : kEmptyWord;
         const uint64_t m01 = a0 < a1 ? a0 : a1;
         const uint64_t m23 = a2 < a3 ? a2 : a3;
         const uint64_t m = m01 < m23 ? m01 : m23;
@@ -188,7 +209,7 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
             for (int u = 0; u < 4; ++u) {
                 if (j0 + u < total) {
                     const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
-                    if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(pp[u].w)));
+                    if (d2 <= gate2) top.insert(word(d2, __float_as_uint(pp[u].w)));
                 }
             }
         }
@@ -200,8 +221,8 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
         if (clr > 0.f) {
             if (clr >= r_gate) return true;   // every point within the gate has been seen
             const uint64_t kth = top.v[K - 1];
-            if (kth != ~0ull) {
-                const float kkey = __uint_as_float((uint32_t)(kth >> 32));
+            if (kth != kEmptyWord) {
+                const float kkey = word_key(kth);
                 if (kkey < clr * clr * (1.f - 1e-6f)) return true;
             }
         }
@@ -249,7 +270,7 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
                     for (uint32_t i = 0; i < cnt; ++i) {
                         const float4 p = g.spts[start + i];
                         const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-                        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+                        if (d2 <= gate2) top.insert(word(d2, __float_as_uint(p.w)));
                     }
                 }
             }
@@ -392,7 +413,7 @@ __device__ __forceinline__ Sym3 raw_from_topk(const TopK<K>& top, int k, const f
             const int j = kGroup * jj + l;
             // a slot stays empty only when fewer than k neighbours have a
             // finite distance (non-finite input, reported through the error word)
-            if (j >= K - k && top.v[j] != ~0ull) add_moments(part[l], top.v[j], xyz, stride, qx, qy, qz);
+            if (j >= K - k && top.v[j] != kEmptyWord) add_moments(part[l], top.v[j], xyz, stride, qx, qy, qz);
         }
     }
     float m[10];
@@ -432,7 +453,7 @@ __device__ __forceinline__ Sym3 raw_from_topk_group(const TopK<K>& top, int k, i
 #pragma unroll
     for (int jj = 0; jj < K / kGroup; ++jj) {
         const uint64_t v = lane_slot<K>(top, jj, l);
-        if (kGroup * jj + l >= K - k && v != ~0ull) add_moments(m, v, xyz, stride, qx, qy, qz);
+        if (kGroup * jj + l >= K - k && v != kEmptyWord) add_moments(m, v, xyz, stride, qx, qy, qz);
     }
     // lane l holds s_l; after the two exchanges every lane holds
     // (s0 + s1) + (s2 + s3) (additions commute bit for bit)
@@ -490,7 +511,7 @@ __global__ __launch_bounds__(knn_threads<K>()) void k_knn_cov(GridView g, SegSet
     TopK<K> top;
     const bool ok = knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, gate2,
                                   gate * 1.000001f + 1e-6f, top, l, s_lists[threadIdx.x / kGroup]);
-    if (!ok || top.v[K - 1] == ~0ull) {
+    if (!ok || top.v[K - 1] == kEmptyWord) {
         if (l == 0) push_work(work, g.n, 0, s);
         return;
     }
@@ -527,7 +548,7 @@ __global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, Seg
         const float gate2 = gate * gate;
         if (!knn_search<K>(g, sg.h, sg.inv_h, (uint32_t)p << (3 * kCellBits), q.x, q.y, q.z, k, gate2,
                            gate * 1.000001f + 1e-6f, top, l, s_lists[grp], kMaxShell, true) ||
-            top.v[K - 1] == ~0ull) {
+            top.v[K - 1] == kEmptyWord) {
             if (l == 0) push_work(work, g.n, 1, s);
             continue;
         }
@@ -559,10 +580,10 @@ __device__ __forceinline__ void store_knn(const TopK<K>& top, int k, int64_t i, 
     for (int j = 0; j < K; ++j) {
         if (j >= K - k) {
             const uint64_t v = top.v[j];
-            const bool ok = v != ~0ull;
+            const bool ok = v != kEmptyWord;
             const int64_t o = i * k + (j - (K - k));
             idx[o] = ok ? (int32_t)(v & 0xFFFFFFFFu) : -1;
-            d2[o] = ok ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+            d2[o] = ok ? word_key(v) : __builtin_inff();
         }
     }
 }
@@ -601,7 +622,7 @@ __device__ __forceinline__ void full_scan_topk(const GridView& g, int64_t lo, in
     for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
         const float4 p = g.spts[j];
         const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-        if (d2 <= gate2) top.insert(lex(d2, __float_as_uint(p.w)));
+        if (d2 <= gate2) top.insert(word(d2, __float_as_uint(p.w)));
     }
     for (int half = blockDim.x / 2; half >= 1; half >>= 1) {
 #pragma unroll
@@ -614,8 +635,8 @@ __device__ __forceinline__ void full_scan_topk(const GridView& g, int64_t lo, in
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (j < K - k) continue;
-                const uint64_t va = ha < K ? a[ha] : ~0ull;
-                const uint64_t vb = hb < K ? b[hb] : ~0ull;
+                const uint64_t va = ha < K ? a[ha] : kEmptyWord;
+                const uint64_t vb = hb < K ? b[hb] : kEmptyWord;
                 const bool ta = va <= vb;
                 top.v[j] = ta ? va : vb;
                 ha += ta ? 1 : 0;
