@@ -51,13 +51,45 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t mask) {
     return (key * 2654435761u) >> (32 - __popc(mask));
 }
 
+// Loads and stores through a pointer the compiler cannot place in an address
+// space (one read from a descriptor in memory) would be flat instructions;
+// these go through the global address space, where every array of the
+// library lives.
+// (the element moves as a 4-, 8- or 16-byte word of the same size; HIP's
+// vector types cannot be copied out of another address space directly)
+template <int B>
+struct GWord;
+template <>
+struct GWord<4> { typedef uint32_t type; };
+template <>
+struct GWord<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <>
+struct GWord<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+
+template <class T>
+__device__ __forceinline__ T gload(const T* p, int64_t i) {
+    typedef typename GWord<sizeof(T)>::type W;
+    const W w = ((const __attribute__((address_space(1))) W*)p)[i];
+    T r;
+    __builtin_memcpy(&r, &w, sizeof(T));
+    return r;
+}
+
+template <class T>
+__device__ __forceinline__ void gstore(T* p, int64_t i, const T& v) {
+    typedef typename GWord<sizeof(T)>::type W;
+    W w;
+    __builtin_memcpy(&w, &v, sizeof(T));
+    ((__attribute__((address_space(1))) W*)p)[i] = w;
+}
+
 // Cell table lookup: entry = {key, start, count, -}.  Returns count (0 if the
 // cell is empty) and writes its start offset into the cell-sorted arrays.
 __device__ __forceinline__ uint32_t cell_lookup(const uint4* __restrict__ table, uint32_t mask,
                                                 uint32_t key, uint32_t& start) {
     uint32_t s = hash_slot(key, mask);
     while (true) {
-        const uint4 e = table[s];
+        const uint4 e = gload(table, s);
         if (e.x == key) {
             start = e.y;
             return e.z;
@@ -79,10 +111,35 @@ __device__ __forceinline__ float rank_key(float qx, float qy, float qz, float px
     return s + dz * dz;
 }
 
-// (key, index) packed so that unsigned integer order is the lexicographic
-// order: non-negative floats order like their bit patterns.
-__device__ __forceinline__ uint64_t lex(float key, uint32_t idx) {
-    return ((uint64_t)__float_as_uint(key) << 32) | (uint64_t)idx;
+// Candidate words: (FP32 key bits + 2^20) << 32 | index.  Unsigned integer
+// order is the (key, index) order, and the offset makes every word the bit
+// pattern of a positive normal double (exponent field 0x001 .. 0x7F9 for keys
+// from +0 to +inf), whose floating-point order is the same: the minimum and
+// maximum of two words are single v_min_f64 / v_max_f64 instructions.  The
+// empty word is +inf, above every word.
+constexpr uint32_t kWordBias = 1u << 20;
+constexpr uint64_t kEmptyWord = 0x7FF0000000000000ull;
+
+__device__ __forceinline__ uint64_t word(float key, uint32_t idx) {
+    return ((uint64_t)(__float_as_uint(key) + kWordBias) << 32) | (uint64_t)idx;
+}
+
+__device__ __forceinline__ float word_key(uint64_t w) { return __uint_as_float((uint32_t)(w >> 32) - kWordBias); }
+
+// Minimum and maximum of two words, written as the instructions on the raw
+// registers: as doubles the words (no NaN, no denormal) compare exactly like
+// the integers, and the compiler's own fmin / fmax would first quieten every
+// operand.
+__device__ __forceinline__ uint64_t wmin(uint64_t a, uint64_t b) {
+    uint64_t r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ uint64_t wmax(uint64_t a, uint64_t b) {
+    uint64_t r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
 __device__ __forceinline__ bool finite3(float x, float y, float z) {

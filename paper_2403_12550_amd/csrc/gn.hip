@@ -74,40 +74,41 @@ __device__ __forceinline__ double column_sum(const float* col, int n, int stride
 // and d2 that bound, |q' - q| < (d2 - d1) / 2 keeps every other mean farther
 // than the nearest one (margins cover the FP32 keys and coordinates);
 // free_r < 0 when there is no correspondence or no margin.
-__device__ __forceinline__ float key_of(uint64_t w) {
-    return w == ~0ull ? FLT_MAX : __uint_as_float((uint32_t)(w >> 32));
-}
+__device__ __forceinline__ float key_of(uint64_t w) { return w == kEmptyWord ? FLT_MAX : word_key(w); }
 
 __device__ __forceinline__ void group_min(uint64_t& best, int32_t& pos) {
 #pragma unroll
     for (int o = 1; o < kGroup; o <<= 1) {
         const uint64_t ob = __shfl_xor(best, o, 64);
         const int32_t op = __shfl_xor(pos, o, 64);
-        if (ob < best) {
-            best = ob;
-            pos = op;
-        }
+        pos = ob < best ? op : pos;
+        best = wmin(best, ob);
     }
 }
 
-// As group_min, also combining each lane's second-best key and pruned-cell bound.
-__device__ __forceinline__ void group_min2(uint64_t& best, int32_t& pos, float& second, float& minlb) {
+// As group_min, also combining each lane's second-best word and pruned-cell
+// bound (a word held by both lanes, such as the shared hint, counts once).
+__device__ __forceinline__ void group_min2(uint64_t& best, int32_t& pos, uint64_t& sec, float& minlb) {
 #pragma unroll
     for (int o = 1; o < kGroup; o <<= 1) {
         const uint64_t ob = __shfl_xor(best, o, 64);
         const int32_t op = __shfl_xor(pos, o, 64);
-        const float os = __shfl_xor(second, o, 64);
+        const uint64_t os = __shfl_xor(sec, o, 64);
         const float om = __shfl_xor(minlb, o, 64);
-        second = fminf(second, os);
         minlb = fminf(minlb, om);
-        if (ob < best) {
-            if (ob != best) second = fminf(second, key_of(best));
-            best = ob;
-            pos = op;
-        } else if (ob != best) {
-            second = fminf(second, key_of(ob));
-        }
+        sec = wmin(wmin(sec, os), ob == best ? kEmptyWord : wmax(best, ob));
+        pos = ob < best ? op : pos;
+        best = wmin(best, ob);
     }
+}
+
+// One candidate at sorted position pj with word v: the best word and its
+// position, and with TRACK2 the second-best word, all without branches.
+template <bool TRACK2>
+__device__ __forceinline__ void take(uint64_t v, int32_t pj, uint64_t& best, int32_t& pos, uint64_t& sec) {
+    pos = v < best ? pj : pos;
+    if (TRACK2) sec = wmin(sec, wmax(best, v));
+    best = wmin(best, v);
 }
 
 // `hint` (a map position, or -1) is a candidate evaluated first, typically the
@@ -118,14 +119,14 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                                            float* free_r = nullptr) {
     const GridView& g = m.g;
     const bool fin = finite3(qx, qy, qz);
-    uint64_t best = ~0ull;
+    uint64_t best = kEmptyWord, sec = kEmptyWord;
     int32_t pos = -1;
-    float second = FLT_MAX, minlb = FLT_MAX;
+    float minlb = FLT_MAX;
     // every lane starts from the hint (equal words are merged once by the
     // group reduction, and the lane owning the hint's cell skips it there)
     if (fin && hint >= 0 && hint < g.n) {
-        const float4 p = g.spts[hint];
-        best = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
+        const float4 p = gload(g.spts, hint);
+        best = word(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
         pos = hint;
     }
     const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, g.inv_h);
@@ -141,16 +142,10 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
         const uint32_t cnt = cell_lookup(g.table, g.mask, cell_key(cx, cy, cz), start);
         for (uint32_t j = 0; j < cnt; ++j) {
             const int32_t pj = (int32_t)(start + j);
-            if (TRACK2 && pj == pos) continue;   // the hint, already counted
-            const float4 p = g.spts[pj];
-            const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
-            if (v < best) {
-                if (TRACK2) second = fminf(second, key_of(best));
-                best = v;
-                pos = pj;
-            } else if (TRACK2) {
-                second = fminf(second, key_of(v));
-            }
+            const float4 p = gload(g.spts, pj);
+            uint64_t v = word(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
+            if (TRACK2) v = pj == pos ? kEmptyWord : v;   // the hint, already counted
+            take<TRACK2>(v, pj, best, pos, sec);
         }
     };
     if (fin) {
@@ -162,12 +157,12 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             // four cells, so that every lane prunes the rest with the group's
             // bound (a hint already gives every lane a tight bound)
             if (j == l && hint < 0) {
-                if (TRACK2) group_min2(best, pos, second, minlb);
+                if (TRACK2) group_min2(best, pos, sec, minlb);
                 else group_min(best, pos);
             }
         }
     }
-    if (TRACK2) group_min2(best, pos, second, minlb);
+    if (TRACK2) group_min2(best, pos, sec, minlb);
     else group_min(best, pos);
     if (!fin) {
         if (free_r) *free_r = -1.f;
@@ -185,7 +180,7 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                 clr_end = clr;
                 break;
             }
-            if (best != ~0ull) {
+            if (best != kEmptyWord) {
                 const float bk = key_of(best);
                 if (bk < clr * clr * (1.f - 1e-6f)) {
                     clr_end = clr;
@@ -195,22 +190,15 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
         }
         if (R >= max_shell) {
             // full scan (exact by construction), split across the group
-            best = ~0ull;
+            best = kEmptyWord;
+            sec = kEmptyWord;
             pos = -1;
-            second = FLT_MAX;
             minlb = FLT_MAX;
             for (int32_t j = l; j < g.n; j += kGroup) {
-                const float4 p = g.spts[j];
-                const uint64_t v = lex(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
-                if (v < best) {
-                    if (TRACK2) second = fminf(second, key_of(best));
-                    best = v;
-                    pos = j;
-                } else if (TRACK2) {
-                    second = fminf(second, key_of(v));
-                }
+                const float4 p = gload(g.spts, j);
+                take<TRACK2>(word(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w)), j, best, pos, sec);
             }
-            if (TRACK2) group_min2(best, pos, second, minlb);
+            if (TRACK2) group_min2(best, pos, sec, minlb);
             else group_min(best, pos);
             break;
         }
@@ -223,7 +211,7 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                         if ((idx & (kGroup - 1)) == l) scan(c.x + dx, c.y + dy, c.z + dz);
                         ++idx;
                     }
-        if (TRACK2) group_min2(best, pos, second, minlb);
+        if (TRACK2) group_min2(best, pos, sec, minlb);
         else group_min(best, pos);
     }
     const float bk = key_of(best);
@@ -231,7 +219,7 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
     if (TRACK2 && free_r) {
         float fr = -1.f;
         if (res >= 0) {
-            const float k2 = fminf(fminf(second, minlb), clr_end * clr_end);
+            const float k2 = fminf(fminf(key_of(sec), minlb), clr_end * clr_end);
             const float d1 = sqrtf(bk), d2 = sqrtf(k2);
             const float mag = fmaxf(fmaxf(fabsf(qx), fabsf(qy)), fabsf(qz));
             fr = 0.5f * (d2 * (1.f - 1e-5f) - d1 * (1.f + 1e-5f)) - 4e-6f * (1.f + mag);
@@ -254,15 +242,15 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     float x, y, z;
     const float* cv;
     if (P.ssrc) {
-        const float4 p4 = P.ssrc[i];
+        const float4 p4 = gload(P.ssrc, i);
         x = p4.x;
         y = p4.y;
         z = p4.z;
         cv = P.sscov;
     } else {
-        x = P.src[i];
-        y = P.src[n + i];
-        z = P.src[2 * n + i];
+        x = gload(P.src, i);
+        y = gload(P.src, n + i);
+        z = gload(P.src, 2 * n + i);
         cv = P.scov;
     }
     const float qx = R[0] * x + R[1] * y + R[2] * z + t[0];
@@ -272,32 +260,32 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     // the previous iteration's match stands while q stays within the radius
     // its search certified (the nearest mean cannot have changed); otherwise
     // search again
-    const int32_t hint = P.nn_prev[i];
+    const int32_t hint = gload((const int32_t*)P.nn_prev, i);
     bool reuse = false;
     if (hint >= 0) {
-        const float4 cq = P.nn_cache[i];
+        const float4 cq = gload((const float4*)P.nn_cache, i);
         const float ex = qx - cq.x, ey = qy - cq.y, ez = qz - cq.z;
         reuse = sqrtf(ex * ex + ey * ey + ez * ez) < cq.w;
     }
     int32_t pos;
     if (reuse) {
-        const float4 p = map.g.spts[hint];
+        const float4 p = gload(map.g.spts, hint);
         pos = rank_key(qx, qy, qz, p.x, p.y, p.z) <= map.r_max2 ? hint : -1;
     } else {
         float free_r;
         pos = nearest<true>(map, qx, qy, qz, l, hint, &free_r);
         if (l == 0) {
-            P.nn_prev[i] = pos;
-            P.nn_cache[i] = make_float4(qx, qy, qz, free_r);
+            gstore(P.nn_prev, i, pos);
+            gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
         }
     }
     if (pos < 0) return false;
-    const float4 mu = map.g.spts[pos];
-    const float4 ca = map.scov[2 * pos];
-    const float4 cb = map.scov[2 * pos + 1];
+    const float4 mu = gload(map.g.spts, pos);
+    const float4 ca = gload(map.scov, 2 * (int64_t)pos);
+    const float4 cb = gload(map.scov, 2 * (int64_t)pos + 1);
     // source covariance rotated: A = R Cs, S = A R^T
-    const float c00 = cv[i], c01 = cv[n + i], c02 = cv[2 * n + i];
-    const float c11 = cv[3 * n + i], c12 = cv[4 * n + i], c22 = cv[5 * n + i];
+    const float c00 = gload(cv, i), c01 = gload(cv, n + i), c02 = gload(cv, 2 * n + i);
+    const float c11 = gload(cv, 3 * n + i), c12 = gload(cv, 4 * n + i), c22 = gload(cv, 5 * n + i);
     const float a00 = R[0] * c00 + R[1] * c01 + R[2] * c02;
     const float a01 = R[0] * c01 + R[1] * c11 + R[2] * c12;
     const float a02 = R[0] * c02 + R[1] * c12 + R[2] * c22;

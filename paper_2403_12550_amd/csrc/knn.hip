@@ -21,22 +21,8 @@ namespace gicp {
 
 namespace {
 
-// Candidate words: (FP32 key bits + 2^20) << 32 | original index.  Unsigned
-// integer order is the (key, index) order, and the offset makes every word the
-// bit pattern of a positive normal double (exponent field 0x001 .. 0x7F9 for
-// keys from +0 to +inf), whose floating-point order is the same; the sorted
-// insertion below runs on v_min_f64 / v_max_f64.  The empty slot is +inf,
-// above every word.
-constexpr uint32_t kWordBias = 1u << 20;
-constexpr uint64_t kEmptyWord = 0x7FF0000000000000ull;
-
-__device__ __forceinline__ uint64_t word(float key, uint32_t idx) {
-    return ((uint64_t)(__float_as_uint(key) + kWordBias) << 32) | (uint64_t)idx;
-}
-
-__device__ __forceinline__ float word_key(uint64_t w) { return __uint_as_float((uint32_t)(w >> 32) - kWordBias); }
-
-// Sorted list of the best candidates as words.  For a runtime k < K the first
+// Sorted list of the best candidates as words (FP32 key, original index; the
+// word encoding orders like doubles).  For a runtime k < K the first
 // K - k slots hold zero words (+0.0), which sort before every candidate and
 // never move, so the k best always occupy slots [K - k, K) and the k-th best
 // is the last slot (a static register index).
