@@ -93,9 +93,7 @@ __device__ __forceinline__ void merge_lists(TopK<K>& top, int k, int l, uint64_t
         const uint64_t a1 = h1 < K ? lists[1 * K + h1] : kEmptyWord;
         const uint64_t a2 = h2 < K ? lists[2 * K + h2] : kEmptyWord;
         const uint64_t a3 = h3 < K ? lists[3 * K + h3] : kEmptyWord;
-        const uint64_t m01 = a0 < a1 ? a0 : a1;
-        const uint64_t m23 = a2 < a3 ? a2 : a3;
-        const uint64_t m = m01 < m23 ? m01 : m23;
+        const uint64_t m = wmin(wmin(a0, a1), wmin(a2, a3));
         top.v[j] = m;
         h0 += (m == a0) ? 1 : 0;
         h1 += (m == a1) ? 1 : 0;
@@ -166,37 +164,52 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
             }
             total += ct[q];
         }
+        // the lane's non-empty cells, compacted through its words of `lists`
+        // (free until the merge below) and read back as a register queue that
+        // shifts by one at every change of cell, so that no register array is
+        // indexed by a lane-dependent value
+        static_assert(K >= kPer, "the compaction needs a list word per cell");
+        uint64_t* const mine = lists + l * K;
+        int nc = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (ct[q] > 0) {
+                mine[nc] = ((uint64_t)ct[q] << 32) | (uint64_t)st[q];
+                ++nc;
+            }
+        }
+        uint64_t cq[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) cq[t] = mine[t];   // slots from nc on are never consumed
         // one flat loop over all of the lane's candidates: the trip count is
         // the lane's candidate total, so the lanes of a wavefront stay close
         // in work (a loop per cell would cost every wavefront the sum over
-        // cells of the largest count among its lanes); loads four at a time
-        int q = 0;
-        uint32_t cs = 0, cl = 0;
+        // cells of the largest count among its lanes); four candidates a
+        // trip, their loads issued together
+        uint32_t cs = 0, cl = 0;   // position and remaining count in the current cell
         for (uint32_t j0 = 0; j0 < total; j0 += 4) {
+            uint32_t pos[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool valid = j0 + u < total;
+                if (valid && cl == 0) {
+                    cs = (uint32_t)cq[0];
+                    cl = (uint32_t)(cq[0] >> 32);
+#pragma unroll
+                    for (int t = 0; t + 1 < kPer; ++t) cq[t] = cq[t + 1];
+                }
+                pos[u] = valid ? cs : 0u;   // position 0 exists whenever total > 0
+                cs += valid ? 1u : 0u;
+                cl -= valid ? 1u : 0u;
+            }
             float4 pp[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (j0 + u < total) {
-                    while (cl == 0 && q < kPer) {
-#pragma unroll
-                        for (int t = 0; t < kPer; ++t)
-                            if (q == t) {
-                                cs = st[t];
-                                cl = ct[t];
-                            }
-                        ++q;
-                    }
-                    pp[u] = g.spts[cs];
-                    ++cs;
-                    --cl;
-                }
-            }
+            for (int u = 0; u < 4; ++u) pp[u] = g.spts[pos[u]];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (j0 + u < total) {
-                    const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
-                    if (d2 <= gate2) top.insert(word(d2, __float_as_uint(pp[u].w)));
-                }
+                const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
+                const uint64_t w = word(d2, __float_as_uint(pp[u].w));   // keeps the four loads whole
+                if (j0 + u < total && d2 <= gate2) top.insert(w);
             }
         }
     }
