@@ -52,17 +52,31 @@ struct TopK {
     }
 };
 
+// Scan the cnt cell-sorted points from `start` into the top-k, their loads
+// issued four at a time (a cell's points are contiguous), so that a run of
+// candidates costs a quarter of the dependent memory round trips.
+template <int K>
+__device__ __forceinline__ void scan_run(const GridView& g, uint32_t start, uint32_t cnt, float qx, float qy,
+                                         float qz, float gate2, TopK<K>& top) {
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 4) {
+        float4 pp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pp[u] = g.spts[start + (i0 + u < cnt ? i0 + u : 0u)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
+            if (i0 + u < cnt && d2 <= gate2) top.insert(word(d2, __float_as_uint(pp[u].w)));
+        }
+    }
+}
+
 // Scan one cell into the top-k.
 template <int K>
 __device__ __forceinline__ void scan_cell(const GridView& g, uint32_t key, float qx, float qy, float qz,
                                           float gate2, TopK<K>& top) {
     uint32_t start = 0;
     const uint32_t cnt = cell_lookup(g.table, g.mask, key, start);
-    for (uint32_t j = 0; j < cnt; ++j) {
-        const float4 p = g.spts[start + j];
-        const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-        if (d2 <= gate2) top.insert(word(d2, __float_as_uint(p.w)));
-    }
+    scan_run<K>(g, start, cnt, qx, qy, qz, gate2, top);
 }
 
 // Current pruning bound: the k-th key once the list is full (else +inf),
@@ -266,11 +280,7 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
                         cnt = 0;
                         if (ent[b].x != kEmptyKey) cnt = cell_lookup(g.table, g.mask, key[b], start);
                     }
-                    for (uint32_t i = 0; i < cnt; ++i) {
-                        const float4 p = g.spts[start + i];
-                        const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-                        if (d2 <= gate2) top.insert(word(d2, __float_as_uint(p.w)));
-                    }
+                    scan_run<K>(g, start, cnt, qx, qy, qz, gate2, top);
                 }
             }
         }
@@ -618,10 +628,22 @@ template <int K>
 __device__ __forceinline__ void full_scan_topk(const GridView& g, int64_t lo, int64_t hi, float qx, float qy,
                                                float qz, int k, float gate2, TopK<K>& top, uint64_t* lists) {
     top.init(k);
-    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
-        const float4 p = g.spts[j];
-        const float d2 = rank_key(qx, qy, qz, p.x, p.y, p.z);
-        if (d2 <= gate2) top.insert(word(d2, __float_as_uint(p.w)));
+    // eight points a trip, their loads issued together: a query scans the
+    // whole cloud alone, so the loop is bound by memory round trips
+    constexpr int kU = 8;
+    const int64_t stride = blockDim.x;
+    for (int64_t j0 = lo + threadIdx.x; j0 < hi; j0 += stride * kU) {
+        float4 pp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t j = j0 + u * stride;
+            pp[u] = g.spts[j < hi ? j : j0];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
+            if (j0 + u * stride < hi && d2 <= gate2) top.insert(word(d2, __float_as_uint(pp[u].w)));
+        }
     }
     for (int half = blockDim.x / 2; half >= 1; half >>= 1) {
 #pragma unroll
