@@ -486,10 +486,15 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
     double* E = L;
     double* T = H;
     exp_se3(xi, E);
+    // the current pose, read once (its rows are loaded together)
+    double P[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) P[i] = st->pose[i];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
             double s = 0.0;
-            for (int k = 0; k < 4; ++k) s += E[4 * i + k] * st->pose[4 * k + j];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s += E[4 * i + k] * P[4 * k + j];
             T[4 * i + j] = s;
         }
     for (int i = 0; i < 16; ++i) st->pose[i] = T[i];
@@ -525,17 +530,30 @@ __device__ void solve_state(const double* __restrict__ partials, int nparts, Reg
     const int t = threadIdx.x;
     // kNumAcc x kSolveParts strided partial sums, whatever the block size, so
     // that every caller reduces in the same order
+    // (eight partials are loaded together and then added in order: the
+    // partials come from other compute units' caches, and one dependent load
+    // per addition would serialise their latency)
+    constexpr int kU = 8;
     for (int q = t; q < kNumAcc * kSolveParts; q += blockDim.x) {
         const int j = q / kSolveParts, p = q % kSolveParts;
-        if (acc == GICP_ACC_FP32) {
-            float f = 0.f;
-            for (int b = p; b < nparts; b += kSolveParts) f += (float)partials[(int64_t)b * kNumAcc + j];
-            s_part[j][p] = (double)f;
-        } else {
-            double v = 0.0;
-            for (int b = p; b < nparts; b += kSolveParts) v += partials[(int64_t)b * kNumAcc + j];
-            s_part[j][p] = v;
+        float f = 0.f;
+        double v = 0.0;
+        for (int b0 = p; b0 < nparts; b0 += kU * kSolveParts) {
+            double x[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int b = b0 + u * kSolveParts;
+                x[u] = b < nparts ? partials[(int64_t)b * kNumAcc + j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (b0 + u * kSolveParts < nparts) {
+                    if (acc == GICP_ACC_FP32) f += (float)x[u];
+                    else v += x[u];
+                }
+            }
         }
+        s_part[j][p] = acc == GICP_ACC_FP32 ? (double)f : v;
     }
     __syncthreads();
     if (t < kNumAcc) {
