@@ -30,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per unit of work ("Kernels and rooflines")
+# algorithmic bytes per unit of work: what the step must read and write, not
+# what a particular search touches
 BYTES_PER_UNIT = {
     0: 72.0,   # linearisation: src xyz 12 + src cov 24 + map mean 12 + map cov 24, per point per iteration
     1: 36.0,   # k-NN covariance: xyz 12 in + cov 24 out, per point
@@ -39,9 +40,16 @@ BYTES_PER_UNIT = {
 }
 GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix sort, table)", 3: "k_gn_solve"}
 # Calibrated HBM bytes per unit from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on
-# this workload (profiles/hbm_traffic__c2_60k_vs_1M_pmc.md); valid for the
-# kernels as they were when the counters were taken.
-TRAFFIC_BYTES_PER_UNIT = {1: 490.2, 0: 66.5}
+# this workload (profiles/hbm_traffic__c2_60k_vs_1M_pmc.md): covariance group
+# per point; linearisation per point and iteration, over the launches that did
+# work.  Valid for the kernels as they were when the counters were taken.
+TRAFFIC_BYTES_PER_UNIT = {1: 489.7, 0: 274.9}
+# Wavefront VALU instructions per unit from rocprofv3 SQ_INSTS_VALU on the same
+# runs (profiles/valu_issue__c2_60k_vs_1M_pmc.md), and the chip's VALU issue
+# peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles
+# (16 lanes a cycle) at 2.4 GHz.
+VALU_INSTS_PER_UNIT = {1: 302.9, 0: 95.8}
+VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def log(*a):
@@ -161,7 +169,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a batch of registrations "
-              "shards with no communication; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "shards with no communication between problems). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -258,6 +266,13 @@ def main():
                 "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                 "bytes_per_unit": BYTES_PER_UNIT[dom], "units_per_launch": units / n,
                 "avg_launch_us": 1e3 * ms / n}
+    valu = VALU_INSTS_PER_UNIT.get(dom)
+    if valu is not None:
+        # the roof the kernel actually meets: vector-ALU instruction issue
+        rate = valu * units / (ms * 1e-3)
+        roofline["alu"] = {"bound": "valu_issue", "achieved": round(rate / 1e9, 2), "peak": VALU_PEAK_INSTS / 1e9,
+                           "unit": "G wave64 VALU instructions/s", "frac": round(rate / VALU_PEAK_INSTS, 4),
+                           "insts_per_unit": valu}
 
     c4 = run_c4(ctx, g) if args.c4 else None
     frontend = None if args.no_frontend else run_frontend(ctx, g, seq, means, covs, args.map_cell)
