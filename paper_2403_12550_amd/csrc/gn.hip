@@ -57,9 +57,21 @@ __device__ __forceinline__ double column_sum(const float* col, int n, int stride
     }
 }
 
+// Lanes per source point in the batched linearisation: the correspondence
+// search's cells are split over them (fewer lanes keep the per-point
+// arithmetic from being repeated on every lane; more shorten each point's
+// chain of dependent lookups).
+#ifndef GICP_LIN_GROUP
+#define GICP_LIN_GROUP 2
+#endif
+constexpr int kLinGroup = GICP_LIN_GROUP;
+constexpr int kLinThreads = kChunk * kLinGroup;
+static_assert(kLinGroup == 1 || kLinGroup == 2 || kLinGroup == 4, "lanes per point: 1, 2 or 4");
+static_assert(kLinThreads >= kNumAcc, "the column sums take one thread per accumulated value");
+
 // Exact 1-NN of q among the map means within the gate, searched by a group of
-// kGroup consecutive lanes (all holding the same q): lane l of the group scans
-// every kGroup-th cell (nearest cells first, skipping cells whose distance
+// G consecutive lanes (all holding the same q): lane l of the group scans
+// every G-th cell (nearest cells first, skipping cells whose distance
 // lower bound exceeds its best key so far or the gate), then the group takes
 // the minimum (FP32 key, original index) with shuffles.  Exactness is proven
 // on the group minimum from the block clearance; otherwise the next shell is
@@ -76,9 +88,10 @@ __device__ __forceinline__ double column_sum(const float* col, int n, int stride
 // free_r < 0 when there is no correspondence or no margin.
 __device__ __forceinline__ float key_of(uint64_t w) { return w == kEmptyWord ? FLT_MAX : word_key(w); }
 
+template <int G>
 __device__ __forceinline__ void group_min(uint64_t& best, int32_t& pos) {
 #pragma unroll
-    for (int o = 1; o < kGroup; o <<= 1) {
+    for (int o = 1; o < G; o <<= 1) {
         const uint64_t ob = __shfl_xor(best, o, 64);
         const int32_t op = __shfl_xor(pos, o, 64);
         pos = ob < best ? op : pos;
@@ -88,9 +101,10 @@ __device__ __forceinline__ void group_min(uint64_t& best, int32_t& pos) {
 
 // As group_min, also combining each lane's second-best word and pruned-cell
 // bound (a word held by both lanes, such as the shared hint, counts once).
+template <int G>
 __device__ __forceinline__ void group_min2(uint64_t& best, int32_t& pos, uint64_t& sec, float& minlb) {
 #pragma unroll
-    for (int o = 1; o < kGroup; o <<= 1) {
+    for (int o = 1; o < G; o <<= 1) {
         const uint64_t ob = __shfl_xor(best, o, 64);
         const int32_t op = __shfl_xor(pos, o, 64);
         const uint64_t os = __shfl_xor(sec, o, 64);
@@ -114,7 +128,7 @@ __device__ __forceinline__ void take(uint64_t v, int32_t pj, uint64_t& best, int
 // `hint` (a map position, or -1) is a candidate evaluated first, typically the
 // point's match of the previous iteration: with its key as the starting bound,
 // pruning skips nearly every cell, and the search stays exact.
-template <bool TRACK2>
+template <bool TRACK2, int G = kGroup>
 __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy, float qz, int l, int32_t hint,
                                            float* free_r = nullptr) {
     const GridView& g = m.g;
@@ -149,7 +163,7 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
         }
     };
     if (fin) {
-        for (int j = l; j < 27; j += kGroup) {
+        for (int j = l; j < 27; j += G) {
             int dx, dy, dz;
             block_offset(j, dx, dy, dz);
             scan(c.x + dx, c.y + dy, c.z + dz);
@@ -157,13 +171,13 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             // four cells, so that every lane prunes the rest with the group's
             // bound (a hint already gives every lane a tight bound)
             if (j == l && hint < 0) {
-                if (TRACK2) group_min2(best, pos, sec, minlb);
-                else group_min(best, pos);
+                if (TRACK2) group_min2<G>(best, pos, sec, minlb);
+                else group_min<G>(best, pos);
             }
         }
     }
-    if (TRACK2) group_min2(best, pos, sec, minlb);
-    else group_min(best, pos);
+    if (TRACK2) group_min2<G>(best, pos, sec, minlb);
+    else group_min<G>(best, pos);
     if (!fin) {
         if (free_r) *free_r = -1.f;
         return -1;
@@ -194,12 +208,12 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             sec = kEmptyWord;
             pos = -1;
             minlb = FLT_MAX;
-            for (int32_t j = l; j < g.n; j += kGroup) {
+            for (int32_t j = l; j < g.n; j += G) {
                 const float4 p = gload(g.spts, j);
                 take<TRACK2>(word(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w)), j, best, pos, sec);
             }
-            if (TRACK2) group_min2(best, pos, sec, minlb);
-            else group_min(best, pos);
+            if (TRACK2) group_min2<G>(best, pos, sec, minlb);
+            else group_min<G>(best, pos);
             break;
         }
         const int S = R + 1;
@@ -208,11 +222,11 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
             for (int dy = -S; dy <= S; ++dy)
                 for (int dx = -S; dx <= S; ++dx)
                     if (max(max(abs(dx), abs(dy)), abs(dz)) == S) {
-                        if ((idx & (kGroup - 1)) == l) scan(c.x + dx, c.y + dy, c.z + dz);
+                        if ((idx & (G - 1)) == l) scan(c.x + dx, c.y + dy, c.z + dz);
                         ++idx;
                     }
-        if (TRACK2) group_min2(best, pos, sec, minlb);
-        else group_min(best, pos);
+        if (TRACK2) group_min2<G>(best, pos, sec, minlb);
+        else group_min<G>(best, pos);
     }
     const float bk = key_of(best);
     const int32_t res = (pos >= 0 && bk <= m.r_max2) ? pos : -1;
@@ -230,12 +244,13 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
 }
 
 // Linearisation of source point i at the pose (R, t), evaluated by a group of
-// kGroup lanes (lane l of the group): on return, v[0..29) holds the point's
+// G lanes (lane l of the group): on return, v[0..29) holds the point's
 // 21 unique terms of J^T M J, the 6 of J^T M d, d^T M d and 1 (the inlier
 // count); the return value is false (and v untouched) when the point has no
 // correspondence within r_max or a singular combined covariance.
 // Point i of the problem's processing order: the grid-cell order when the
 // problem carries its sorted source (ssrc, sscov), else the caller's order.
+template <int G>
 __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, const float* R, const float* t,
                                                 float* v, int l) {
     const int64_t n = P.n;
@@ -273,7 +288,7 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
         pos = rank_key(qx, qy, qz, p.x, p.y, p.z) <= map.r_max2 ? hint : -1;
     } else {
         float free_r;
-        pos = nearest<true>(map, qx, qy, qz, l, hint, &free_r);
+        pos = nearest<true, G>(map, qx, qy, qz, l, hint, &free_r);
         if (l == 0) {
             gstore(P.nn_prev, i, pos);
             gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
@@ -349,20 +364,20 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     return true;
 }
 
-// One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, four
+// One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, G
 // lanes per point.  The group's first lane stores the point's 29 values in an
 // LDS row (zeros when it is not an inlier); threads 0..28 then sum one column
 // each over the 64 rows in a fixed order, and write the chunk's FP64 partial.
-template <int ACC>
+template <int ACC, int G = kGroup>
 __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, const float* R, const float* t,
                                                 double* __restrict__ out) {
     __shared__ float s_val[kChunk][kNumAcc + 1];
-    const int l = threadIdx.x & (kGroup - 1);
-    const int pt = threadIdx.x / kGroup;
+    const int l = threadIdx.x & (G - 1);
+    const int pt = threadIdx.x / G;
     const int64_t i = c * kChunk + pt;
     float v[kNumAcc];
     bool ok = false;
-    if (i < P.n) ok = linearize_point(P, i, R, t, v, l);
+    if (i < P.n) ok = linearize_point<G>(P, i, R, t, v, l);
     if (l == 0) {
 #pragma unroll
         for (int j = 0; j < kNumAcc; ++j) s_val[pt][j] = ok ? v[j] : 0.f;
@@ -704,7 +719,7 @@ __global__ void k_chunk_map(const ProbDev* __restrict__ probs, int nprob, int32_
 }
 
 template <int ACC>
-__global__ __launch_bounds__(kBlock) void k_gn_linearize_batch(const ProbDev* __restrict__ probs,
+__global__ __launch_bounds__(kLinThreads) void k_gn_linearize_batch(const ProbDev* __restrict__ probs,
                                                                const int32_t* __restrict__ chunk_prob,
                                                                double* __restrict__ partials) {
     const int b = blockIdx.x;
@@ -718,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_gn_linearize_batch(const ProbDev* __
     for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
 #pragma unroll
     for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
-    chunk_linearize<ACC>(P, b - P.part0, R, t, partials + (int64_t)b * kNumAcc);
+    chunk_linearize<ACC, kLinGroup>(P, b - P.part0, R, t, partials + (int64_t)b * kNumAcc);
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev* __restrict__ probs,
@@ -849,15 +864,15 @@ hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, int32_t* c
     if (linearize) {
         switch (acc) {
             case GICP_ACC_FP32:
-                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP32>, dim3((unsigned)chunks), dim3(kBlock), 0, s,
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP32>, dim3((unsigned)chunks), dim3(kLinThreads), 0, s,
                                    probs, chunk_prob, partials);
                 break;
             case GICP_ACC_FP64:
-                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP64>, dim3((unsigned)chunks), dim3(kBlock), 0, s,
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP64>, dim3((unsigned)chunks), dim3(kLinThreads), 0, s,
                                    probs, chunk_prob, partials);
                 break;
             default:
-                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_TWOSUM>, dim3((unsigned)chunks), dim3(kBlock), 0,
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_TWOSUM>, dim3((unsigned)chunks), dim3(kLinThreads), 0,
                                    s, probs, chunk_prob, partials);
         }
     }
