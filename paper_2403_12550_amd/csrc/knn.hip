@@ -178,41 +178,86 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
             }
             total += ct[q];
         }
-        // the lane's non-empty cells, compacted through its words of `lists`
-        // (free until the merge below) and read back as a register queue that
-        // shifts by one at every change of cell, so that no register array is
-        // indexed by a lane-dependent value
-        static_assert(K >= kPer, "the compaction needs a list word per cell");
-        uint64_t* const mine = lists + l * K;
-        int nc = 0;
+        // The group's non-empty cells, compacted lane by lane into the group's
+        // words of `lists` (free until the merge below): entry order is lane 0's
+        // cells, then lane 1's, ...  The concatenated candidates of all the
+        // cells are then split evenly over the four lanes (lane l takes
+        // positions [l T / 4, (l + 1) T / 4) of the T candidates), so that the
+        // lanes of a query do equal work whatever the cells' counts.
+        static_assert(kGroup == 4 && K * kGroup > 27, "the group's cells fit its list words");
+        int nz = 0;
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            if (ct[q] > 0) {
-                mine[nc] = ((uint64_t)ct[q] << 32) | (uint64_t)st[q];
-                ++nc;
+        for (int q = 0; q < kPer; ++q) nz += ct[q] > 0u ? 1 : 0;
+        const int lane0 = (int)(threadIdx.x & 63u) & ~(kGroup - 1);
+        uint32_t cnt_of[kGroup];   // candidates of each lane's cells
+        int nz_of[kGroup];         // non-empty cells of each lane
+#pragma unroll
+        for (int m = 0; m < kGroup; ++m) {
+            cnt_of[m] = (uint32_t)__shfl((int)total, lane0 + m, 64);
+            nz_of[m] = __shfl(nz, lane0 + m, 64);
+        }
+        uint32_t S[kGroup + 1];   // candidates before lane m's cells
+        int E[kGroup + 1];        // entries before lane m's cells
+        S[0] = 0;
+        E[0] = 0;
+#pragma unroll
+        for (int m = 0; m < kGroup; ++m) {
+            S[m + 1] = S[m] + cnt_of[m];
+            E[m + 1] = E[m] + nz_of[m];
+        }
+        {
+            int w = l == 0 ? E[0] : l == 1 ? E[1] : l == 2 ? E[2] : E[3];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                if (ct[q] > 0u) {
+                    lists[w] = ((uint64_t)ct[q] << 32) | (uint64_t)st[q];
+                    ++w;
+                }
             }
         }
-        uint64_t cq[kPer];
-#pragma unroll
-        for (int t = 0; t < kPer; ++t) cq[t] = mine[t];   // slots from nc on are never consumed
-        // one flat loop over all of the lane's candidates: the trip count is
-        // the lane's candidate total, so the lanes of a wavefront stay close
-        // in work (a loop per cell would cost every wavefront the sum over
-        // cells of the largest count among its lanes); four candidates a
-        // trip, their loads issued together
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t T = S[kGroup];
+        const uint32_t a0 = (T * (uint32_t)l) / kGroup, a1 = (T * (uint32_t)(l + 1)) / kGroup;
+        const uint32_t n = a1 - a0;
         uint32_t cs = 0, cl = 0;   // position and remaining count in the current cell
-        for (uint32_t j0 = 0; j0 < total; j0 += 4) {
+        int e = 0;                 // the current entry
+        if (n > 0) {
+            // the entry holding position a0: first the lane block, then the cell
+            const int m = (a0 >= S[1] ? 1 : 0) + (a0 >= S[2] ? 1 : 0) + (a0 >= S[3] ? 1 : 0);
+            const uint32_t sm = m == 0 ? S[0] : m == 1 ? S[1] : m == 2 ? S[2] : S[3];
+            const int em = m == 0 ? E[0] : m == 1 ? E[1] : m == 2 ? E[2] : E[3];
+            uint32_t r = a0 - sm;
+            e = em;
+            while (true) {
+                const uint64_t x = lists[e];
+                const uint32_t c = (uint32_t)(x >> 32);
+                if (r < c) {
+                    cs = (uint32_t)x + r;
+                    cl = c - r;
+                    break;
+                }
+                r -= c;
+                ++e;
+            }
+        }
+        // one flat loop over the lane's n candidates, four a trip, their
+        // loads issued together; the next entry is read ahead (the slot after
+        // the last entry is never consumed)
+        uint64_t nxt = lists[e + 1];
+        for (uint32_t j0 = 0; j0 < n; j0 += 4) {
             uint32_t pos[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const bool valid = j0 + u < total;
+                const bool valid = j0 + u < n;
                 if (valid && cl == 0) {
-                    cs = (uint32_t)cq[0];
-                    cl = (uint32_t)(cq[0] >> 32);
-#pragma unroll
-                    for (int t = 0; t + 1 < kPer; ++t) cq[t] = cq[t + 1];
+                    cs = (uint32_t)nxt;
+                    cl = (uint32_t)(nxt >> 32);
+                    ++e;
+                    nxt = lists[e + 1];
                 }
-                pos[u] = valid ? cs : 0u;   // position 0 exists whenever total > 0
+                pos[u] = valid ? cs : 0u;   // position 0 exists whenever n > 0
                 cs += valid ? 1u : 0u;
                 cl -= valid ? 1u : 0u;
             }
@@ -223,9 +268,11 @@ __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv
             for (int u = 0; u < 4; ++u) {
                 const float d2 = rank_key(qx, qy, qz, pp[u].x, pp[u].y, pp[u].z);
                 const uint64_t w = word(d2, __float_as_uint(pp[u].w));   // keeps the four loads whole
-                if (j0 + u < total && d2 <= gate2) top.insert(w);
+                if (j0 + u < n && d2 <= gate2) top.insert(w);
             }
         }
+        // every lane has read the entries before the merge reuses the words
+        __builtin_amdgcn_wave_barrier();
     }
     merge_lists<K>(top, k, l, lists);
     if (!fin) return true;
