@@ -448,6 +448,14 @@ __device__ __forceinline__ void exp_se3(const double xi[6], double T[16]) {
 // LDS (workspace of 72 doubles) so that the single-thread FP64 solve does not
 // raise the register footprint of the kernels that embed it.
 __device__ __noinline__ void solve_update(const double* v, RegState* st, double* H, double* L) {
+    // every field of the state read below, loaded together before any store
+    // (the state was last written on another compute unit: one round trip)
+    const int32_t iters = st->iters + 1;
+    const int32_t max_it = st->max_it;
+    const double conv_rot = st->conv_rot, conv_trans = st->conv_trans;
+    double P[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) P[i] = st->pose[i];
     int q = 0;
     for (int i = 0; i < 6; ++i)
         for (int j = i; j < 6; ++j) {
@@ -459,7 +467,7 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
     for (int j = 0; j < 6; ++j) st->b[j] = v[21 + j];
     st->cost = v[27];
     st->n_inl = v[28];
-    st->iters += 1;
+    st->iters = iters;
     if (v[28] < 6.0) {
         st->status = GICP_E_NO_CORR;
         st->done = 1;
@@ -501,10 +509,6 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
     double* E = L;
     double* T = H;
     exp_se3(xi, E);
-    // the current pose, read once (its rows are loaded together)
-    double P[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) P[i] = st->pose[i];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
             double s = 0.0;
@@ -515,10 +519,10 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
     for (int i = 0; i < 16; ++i) st->pose[i] = T[i];
     const double nw = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
     const double nv = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
-    if (nw < st->conv_rot && nv < st->conv_trans) {
+    if (nw < conv_rot && nv < conv_trans) {
         st->converged = 1;
         st->done = 1;
-    } else if (st->iters >= st->max_it) {
+    } else if (iters >= max_it) {
         st->done = 1;
     }
     for (int i = 0; i < 3; ++i) {
