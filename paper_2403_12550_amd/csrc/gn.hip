@@ -448,14 +448,11 @@ __device__ __forceinline__ void exp_se3(const double xi[6], double T[16]) {
 // LDS (workspace of 72 doubles) so that the single-thread FP64 solve does not
 // raise the register footprint of the kernels that embed it.
 __device__ __noinline__ void solve_update(const double* v, RegState* st, double* H, double* L) {
-    // every field of the state read below, loaded together before any store
+    // the state's scalar fields read below, loaded together before any store
     // (the state was last written on another compute unit: one round trip)
     const int32_t iters = st->iters + 1;
     const int32_t max_it = st->max_it;
     const double conv_rot = st->conv_rot, conv_trans = st->conv_trans;
-    double P[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) P[i] = st->pose[i];
     int q = 0;
     for (int i = 0; i < 6; ++i)
         for (int j = i; j < 6; ++j) {
@@ -473,39 +470,58 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
         st->done = 1;
         return;
     }
-    // Cholesky H = L L^T; a pivot not above 1e-12 * max(diag H) fails
+    // Cholesky H = L L^T; a pivot not above 1e-12 * max(diag H) fails.  The
+    // factor lives in registers (every index below is fixed after unrolling;
+    // H stays in LDS, read off the dependency chain) and each column is
+    // scaled by one reciprocal of its pivot.
+    double Lr[36], inv[6];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) Lr[i] = 0.0;
     double dmax = 0.0;
+#pragma unroll
     for (int i = 0; i < 6; ++i) dmax = fmax(dmax, H[7 * i]);
     const double floor_ = 1e-12 * dmax;
-    for (int i = 0; i < 36; ++i) L[i] = 0.0;
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
         double s = H[7 * j];
-        for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= Lr[6 * j + k] * Lr[6 * j + k];
         if (!(s > floor_) || !isfinite(s)) {
             st->status = GICP_E_DEGENERATE;
             st->done = 1;
             return;
         }
-        L[7 * j] = sqrt(s);
+        Lr[7 * j] = sqrt(s);
+        inv[j] = 1.0 / Lr[7 * j];
+#pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double r = H[6 * i + j];
-            for (int k = 0; k < j; ++k) r -= L[6 * i + k] * L[6 * j + k];
-            L[6 * i + j] = r / L[7 * j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) r -= Lr[6 * i + k] * Lr[6 * j + k];
+            Lr[6 * i + j] = r * inv[j];
         }
     }
     double y[6], xi[6];
+#pragma unroll
     for (int i = 0; i < 6; ++i) {
         double r = v[21 + i];
-        for (int k = 0; k < i; ++k) r -= L[6 * i + k] * y[k];
-        y[i] = r / L[7 * i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) r -= Lr[6 * i + k] * y[k];
+        y[i] = r * inv[i];
     }
+#pragma unroll
     for (int i = 5; i >= 0; --i) {
         double r = y[i];
-        for (int k = i + 1; k < 6; ++k) r -= L[6 * k + i] * xi[k];
-        xi[i] = r / L[7 * i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) r -= Lr[6 * k + i] * xi[k];
+        xi[i] = r * inv[i];
     }
+#pragma unroll
     for (int i = 0; i < 6; ++i) xi[i] = -xi[i];
     // T <- Exp(xi) T, with Exp in L[0..16) and the product in H[0..16) (both free now)
+    double P[16];   // the current pose (its 16 loads issued together)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) P[i] = st->pose[i];
     double* E = L;
     double* T = H;
     exp_se3(xi, E);
@@ -533,7 +549,7 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
 
 namespace {
 
-constexpr int kSolveThreads = 1024;
+constexpr int kSolveThreads = 512;
 constexpr int kSolveParts = 32;
 
 }  // namespace
