@@ -29,30 +29,54 @@ __device__ __forceinline__ void two_sum(float a, float b, float& t, float& err) 
     err = (a - (t - bp)) + (b - bp);
 }
 
-// Fixed-order sum of one column of the chunk's per-point values (n values at
-// stride `stride` in LDS), in the accumulation mode ACC:
+// Fixed-order sum of one column of the chunk's per-point values (kChunk
+// values at stride `stride` in LDS), in the accumulation mode ACC:
 //   TWOSUM: FP32 compensated summation (two-sum of every addition, the
 //           compensations summed alongside), returned as s + c in FP64;
 //   FP32:   plain FP32 summation;
 //   FP64:   FP64 summation of the FP32 values.
+// The sum is split over kSumParts consecutive lanes: lane `part` sums its
+// kChunk / kSumParts rows in order, then the parts are combined pairwise
+// through lane shuffles, ((p0 + p1) + (p2 + p3)); every lane of the four
+// returns the same total (two-sum is exact, so its error term does not depend
+// on the operand order).
+constexpr int kSumParts = 4;
+
 template <int ACC>
-__device__ __forceinline__ double column_sum(const float* col, int n, int stride) {
+__device__ __forceinline__ double column_sum_split(const float* col, int stride, int part) {
+    constexpr int rows = kChunk / kSumParts;
+    const float* c0 = col + part * rows * stride;
     if (ACC == GICP_ACC_TWOSUM) {
         float s = 0.f, c = 0.f;
-        for (int p = 0; p < n; ++p) {
+#pragma unroll
+        for (int p = 0; p < rows; ++p) {
             float t, e;
-            two_sum(s, col[p * stride], t, e);
+            two_sum(s, c0[p * stride], t, e);
             s = t;
             c += e;
+        }
+#pragma unroll
+        for (int o = 1; o < kSumParts; o <<= 1) {
+            const float os = __shfl_xor(s, o, 64), oc = __shfl_xor(c, o, 64);
+            float t, e;
+            two_sum(s, os, t, e);
+            s = t;
+            c = (c + oc) + e;
         }
         return (double)s + (double)c;
     } else if (ACC == GICP_ACC_FP32) {
         float s = 0.f;
-        for (int p = 0; p < n; ++p) s += col[p * stride];
+#pragma unroll
+        for (int p = 0; p < rows; ++p) s += c0[p * stride];
+#pragma unroll
+        for (int o = 1; o < kSumParts; o <<= 1) s += __shfl_xor(s, o, 64);
         return (double)s;
     } else {
         double s = 0.0;
-        for (int p = 0; p < n; ++p) s += (double)col[p * stride];
+#pragma unroll
+        for (int p = 0; p < rows; ++p) s += (double)c0[p * stride];
+#pragma unroll
+        for (int o = 1; o < kSumParts; o <<= 1) s += __shfl_xor(s, o, 64);
         return s;
     }
 }
@@ -67,7 +91,7 @@ __device__ __forceinline__ double column_sum(const float* col, int n, int stride
 constexpr int kLinGroup = GICP_LIN_GROUP;
 constexpr int kLinThreads = kChunk * kLinGroup;
 static_assert(kLinGroup == 1 || kLinGroup == 2 || kLinGroup == 4, "lanes per point: 1, 2 or 4");
-static_assert(kLinThreads >= kNumAcc, "the column sums take one thread per accumulated value");
+static_assert(kLinThreads >= kNumAcc * kSumParts, "the column sums take kSumParts threads per accumulated value");
 
 // Exact 1-NN of q among the map means within the gate, searched by a group of
 // G consecutive lanes (all holding the same q): lane l of the group scans
@@ -383,7 +407,11 @@ __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, con
         for (int j = 0; j < kNumAcc; ++j) s_val[pt][j] = ok ? v[j] : 0.f;
     }
     __syncthreads();
-    if (threadIdx.x < kNumAcc) out[threadIdx.x] = column_sum<ACC>(&s_val[0][threadIdx.x], kChunk, kNumAcc + 1);
+    if (threadIdx.x < kNumAcc * kSumParts) {
+        const int col = threadIdx.x / kSumParts, part = threadIdx.x % kSumParts;
+        const double r = column_sum_split<ACC>(&s_val[0][col], kNumAcc + 1, part);
+        if (part == 0) out[col] = r;
+    }
     __syncthreads();
 }
 
