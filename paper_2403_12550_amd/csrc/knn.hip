@@ -3,9 +3,9 @@
 // neighbours; Sec. 3.1: C = R Lambda^2 R^T, plane and ellipse forms).
 //
 // A group of four consecutive lanes serves one query: the lanes split the
-// cells of the 27-cell block, each keeps its own best candidates in registers
-// as 64-bit (FP32 key, original index) words, sorted, inserted with an
-// unrolled min/max sweep, and the four lists are merged through LDS.
+// candidates of the 27-cell block evenly, each keeps its own best candidates
+// in registers as 64-bit (FP32 key, original index) words, sorted, inserted
+// with an unrolled min/max sweep, and the four lists are merged through LDS.
 // Queries of the self k-NN are the cell-sorted points themselves, so the
 // groups of a wavefront visit the same cells and the candidate reads are
 // served by the vector L1/L2.  After the 27-cell block the group proves
@@ -121,14 +121,16 @@ __device__ __forceinline__ void merge_lists(TopK<K>& top, int k, int l, uint64_t
 constexpr int kShellBatch = 8;   // table slots loaded together per lane in a batched shell scan
 
 // Exact k-NN of q by a group of kGroup consecutive lanes (lane l; all hold
-// q).  Each lane fills its own top-k from every kGroup-th cell of the 27-cell
-// block (nearest cells first; a cell is skipped when its distance lower bound
-// exceeds the lane's current k-th key or the gate), and the four lists are
-// merged, so the group continues converged.  Exactness is then proven from
-// the block clearance; otherwise the lanes split the cells of the next shell
-// the same way, starting from the merged list, and merge again.  Returns
-// false when max_shell shells did not prove the result exact: the caller then
-// hands the query on (to a later pass or to a whole-cloud scan).
+// q).  The lanes look up every kGroup-th cell of the 27-cell block (a cell
+// whose distance lower bound exceeds the gate counts as empty), then split
+// the block's candidates evenly: each lane fills its own top-k from a
+// contiguous quarter of them, and the four lists are merged, so the group
+// continues converged.  Exactness is then proven from the block clearance;
+// otherwise the lanes split the cells of the next shell (every kGroup-th
+// cell, skipping those beyond the current k-th key or the gate), starting
+// from the merged list, and merge again.  Returns false when max_shell shells
+// did not prove the result exact: the caller then hands the query on (to a
+// later pass or to a whole-cloud scan).
 template <int K>
 __device__ __forceinline__ bool knn_search(const GridView& g, float h, float inv_h, uint32_t prefix, float qx,
                                            float qy, float qz, int k, float gate2, float r_gate, TopK<K>& top, int l,
