@@ -55,3 +55,28 @@ def test_host_only_calls(libpath):
     # argument validation happens before any device call
     assert lib.gicp_create(None, 0) == _abi.GICP_E_ARG
     assert lib.gicp_covariances(None, None, 0, 20, 0.0, 1, 1e-3, None, None) == _abi.GICP_E_ARG
+
+
+def test_batch_structs_match_the_header_layout():
+    """The batched binding fills gicp_problem and gicp_stats through numpy
+    structured arrays; their field offsets must be the ctypes (C) ones."""
+    import ctypes as C
+
+    import paper_2403_12550_amd as g
+    assert g._PROBLEM_DT.itemsize == C.sizeof(g.Problem)
+    assert g._STATS_DT.itemsize == C.sizeof(g.Stats)
+    for name, _ in g.Problem._fields_:
+        assert g._PROBLEM_DT.fields[name][1] == getattr(g.Problem, name).offset, name
+    for name, _ in g.Stats._fields_:
+        assert g._STATS_DT.fields[name][1] == getattr(g.Stats, name).offset, name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; N > 1 exits with a message before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
