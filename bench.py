@@ -168,7 +168,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (a batch of registrations "
+        print("bench.py measures one GPU: the library has no multi-GPU path (a batch of registrations "
               "shards with no communication between problems). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
