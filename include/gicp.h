@@ -149,7 +149,7 @@ int gicp_sync_status(gicp_ctx* ctx, void* stream);
 
 /* Estimates a grid cell size for k-NN over `pts` (n points, SoA [3][n]):
  * the 75th percentile, over up to 256 evenly strided sample points, of the
- * distance to the k-th nearest neighbour (brute force), times 1.1.
+ * distance to the k-th nearest neighbour (brute force), times 1.2.
  * Synchronises the stream; writes the result to *cell (host). */
 int gicp_estimate_cell(gicp_ctx* ctx, const float* pts, int64_t n, int k, float* cell, void* stream);
 

@@ -237,7 +237,7 @@ SegSet one_cloud(const float* xyz, int64_t n, float h, float* covs = nullptr, fl
     return S;
 }
 
-// Grid cell size for a k-NN search: 1.1 x the 75th percentile of the k-th
+// Grid cell size for a k-NN search: 1.2 x the 75th percentile of the k-th
 // neighbour distance of 256 strided sample points.  Above kEstimateScan
 // points the distances are taken among every step-th point only, at the
 // neighbour rank that covers the same area on a surface (rank k / step), so
@@ -281,7 +281,7 @@ void estimate_cells(gicp_ctx* ctx, int count, const float* const* xyz, const int
         std::vector<float> v(ctx->h_kth + (int64_t)i * kEstimateSamples,
                              ctx->h_kth + (int64_t)i * kEstimateSamples + ns[i]);
         std::sort(v.begin(), v.end());
-        float c = v[(size_t)(0.75 * (ns[i] - 1))] * 1.1f;
+        float c = v[(size_t)(0.75 * (ns[i] - 1))] * 1.2f;
         if (!(c > 1e-6f) || !std::isfinite(c)) c = 1e-3f;
         cells[i] = c;
     }
