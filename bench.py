@@ -43,12 +43,12 @@ GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix 
 # this workload (profiles/hbm_traffic__c2_60k_vs_1M_pmc.md): covariance group
 # per point; linearisation per point and iteration, over the launches that did
 # work.  Valid for the kernels as they were when the counters were taken.
-TRAFFIC_BYTES_PER_UNIT = {1: 490.7, 0: 301.6}
+TRAFFIC_BYTES_PER_UNIT = {1: 448.9, 0: 300.3}
 # Wavefront VALU instructions per unit from rocprofv3 SQ_INSTS_VALU on the same
 # runs (profiles/valu_issue__c2_60k_vs_1M_pmc.md), and the chip's VALU issue
 # peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles
 # (16 lanes a cycle) at 2.4 GHz.
-VALU_INSTS_PER_UNIT = {1: 253.2, 0: 82.6}
+VALU_INSTS_PER_UNIT = {1: 258.0, 0: 82.6}
 VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
 
 
