@@ -12,7 +12,7 @@ What it computes, following the paper "RGBD GS-ICP SLAM" (Ha, Yeon, Yu):
                    covariance of its k nearest neighbours (Sec. 3, definition
                    of the Gaussian set G = {X, C}).
 * ``covariance``   that covariance, its decomposition C = R Lambda^2 R^T and
-                   the plane / ellipse scale regularisations (Sec. 3.1,
+                   the plane / ellipse scale regularisations (Sec. 3.1.1,
                    Scale Regularization).
 * ``se3``          the SE(3) exponential used for the pose update, and the
                    rotation logarithm used for error metrics.

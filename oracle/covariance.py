@@ -1,7 +1,7 @@
 """Oracle: per-point covariances and scale regularisation (test infrastructure only).
 
 Paper, Sec. 3: the covariance C of a point x is the covariance matrix of its k
-nearest neighbours.  Sec. 3.1 (Scale Regularization): C = R Lambda^2 R^T with
+nearest neighbours.  Sec. 3.1.1 (Scale Regularization): C = R Lambda^2 R^T with
 Lambda = diag(s2, s1, s0), s2 > s1 > s0 (for a symmetric PSD matrix the SVD is
 its eigendecomposition, so ``numpy.linalg.eigh`` is used); the plane
 regularisation replaces the scales by (1, 1, eps) so that each Gaussian is a
@@ -54,14 +54,20 @@ def neighbourhood_covariance(points: np.ndarray, nbr_idx: np.ndarray) -> np.ndar
 
 
 def regularise(C: np.ndarray, mode: int, eps: float = 1e-3) -> np.ndarray:
-    """Scale regularisation of covariances C [n,3,3] (Sec. 3.1)."""
+    """Scale regularisation of covariances C [n,3,3] (Sec. 3.1.1)."""
     if mode == REG_NONE:
         return C.copy()
     lam, V = np.linalg.eigh(C)                              # ascending: lam0 <= lam1 <= lam2
     if mode == REG_PLANE:
         scales2 = np.broadcast_to(np.array([eps, 1.0, 1.0]), lam.shape)
     elif mode == REG_ELLIPSE:
-        scales2 = lam / lam[:, 1:2]
+        # the median scale squared is the middle eigenvalue; where it vanishes
+        # (all neighbours collinear) the paper's division is undefined: it is
+        # clamped at 1e-6 of the largest eigenvalue, and an all-zero
+        # covariance (all neighbours coincide) stays zero
+        den = np.maximum(lam[:, 1:2], 1e-6 * lam[:, 2:3])
+        with np.errstate(invalid="ignore", divide="ignore"):
+            scales2 = np.where(den > 0, lam / np.where(den > 0, den, 1.0), 0.0)
     else:
         raise ValueError(f"unknown regularisation mode {mode}")
     return np.einsum("nij,nj,nkj->nik", V, scales2, V)
@@ -89,5 +95,5 @@ def eigen_gap(C: np.ndarray) -> np.ndarray:
 
 def regularise6(c6: np.ndarray, mode: int, eps: float = 1e-3) -> np.ndarray:
     """``regularise`` on covariances in the [n,6] layout (used for map Gaussians
-    that arrive with their own covariances, Sec. 3.1)."""
+    that arrive with their own covariances, Sec. 3.1.1)."""
     return to6(regularise(from6(c6), mode, eps))

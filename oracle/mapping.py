@@ -1,19 +1,19 @@
 """Oracle: keyframe decision, scale aligning and the Gaussians a keyframe adds
 to the map (test infrastructure only).
 
-Paper, Sec. 3.2 (Keyframe Selection): the proportion of source points that
+Paper, Sec. 3.1.2 (Keyframe Selection): the proportion of source points that
 have a correspondence in the map (a map Gaussian within the distance
 threshold at the estimated pose, a by-product of G-ICP) decides keyframes: a
 frame whose proportion falls below a threshold is a keyframe.  Only the
 frame's Gaussians that do not overlap the existing map are added to it.
 
-Paper, Sec. 3.3 (Scale Aligning): before insertion the scales of a frame's
+Paper, Sec. 3.2.1 (Scale Aligning): before insertion the scales of a frame's
 Gaussians are normalised by depth, Lambda'' = Lambda' / z^p, where Lambda' is
-the ellipse-regularised scale (Sec. 3.1); the ablation (Table: scale
+the ellipse-regularised scale (Sec. 3.1.1); the ablation (Table: scale
 aligning) selects p = 1.5.  With C = R Lambda^2 R^T this divides the
 covariance by z^(2p).
 
-Paper, Sec. 3.3 (Additional Keyframe Selection for Mapping): besides the
+Paper, Sec. 3.2.2 (Additional Keyframe Selection for Mapping): besides the
 tracking keyframes, mapping-only keyframes are taken at a shorter interval,
 and a tracking keyframe is forced when none was selected for a longer one
 (the text uses 10 and 30 frames).

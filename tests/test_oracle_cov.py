@@ -1,5 +1,5 @@
 """Pins of the oracle's covariances (Sec. 3: covariance of the k nearest
-neighbours; Sec. 3.1: C = R Lambda^2 R^T, plane and ellipse regularisation)."""
+neighbours; Sec. 3.1.1: C = R Lambda^2 R^T, plane and ellipse regularisation)."""
 import json
 import os
 
@@ -104,3 +104,17 @@ def test_sum_decomposition_reconstructs():
     C = A @ A.transpose(0, 2, 1)
     lam, V = np.linalg.eigh(C)
     assert np.abs(np.einsum("nij,nj,nkj->nik", V, lam, V) - C).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", ["collinear", "coincident", "thin_needle"])
+def test_golden_ellipse_degenerate(case):
+    """The ellipse form where the middle eigenvalue vanishes (collinear or
+    coincident neighbours), and at the clamp's edge."""
+    g = json.load(open(os.path.join(GOLD, "cov_ellipse_degenerate.json")))[case]
+    pts = np.array(g["points"], np.float64)
+    idx = np.tile(np.arange(len(pts)), (len(pts), 1))
+    C = oc.neighbourhood_covariance(pts, idx)
+    got = oc.to6(oc.regularise(C, oc.REG_ELLIPSE))
+    exp = np.array(g["expected_cov6_ellipse_each"])
+    for row in got:
+        assert np.allclose(row, exp, rtol=1e-9, atol=1e-9), (case, row)
