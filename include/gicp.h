@@ -6,7 +6,7 @@
  *      radix sort (Sec. 3: the covariance of a point is the covariance matrix
  *      of its k nearest neighbours; correspondences come from nearest-
  *      neighbour search);
- *   2. per-point covariances with scale regularisation (Sec. 3.1, Scale
+ *   2. per-point covariances with scale regularisation (Sec. 3.1.1, Scale
  *      Regularization: C = R Lambda^2 R^T; plane form with scales (1,1,eps),
  *      ellipse form with scales divided by their median);
  *   3. Gauss-Newton minimisation of the Mahalanobis objective of
@@ -53,7 +53,8 @@ extern "C" {
 
 typedef enum gicp_status {
     GICP_OK = 0,
-    GICP_E_ARG = 1,         /* null pointer, n < k, k outside [1,64], n <= 0, bad mode */
+    GICP_E_ARG = 1,         /* null pointer, n < k, k outside [3,64] for a covariance ([1,64] for a
+                               search), n <= 0, bad mode */
     GICP_E_NONFINITE = 2,   /* a NaN/Inf coordinate or covariance entry was seen */
     GICP_E_NO_CORR = 3,     /* fewer than 6 correspondences within r_max */
     GICP_E_DEGENERATE = 4,  /* Cholesky of H failed: a pivot <= 1e-12 * max(diag H) */
@@ -64,8 +65,8 @@ typedef enum gicp_status {
 
 typedef enum gicp_reg_mode {
     GICP_REG_NONE = 0,      /* raw k-NN covariance */
-    GICP_REG_PLANE = 1,     /* eigenvalues replaced by (1, 1, eps): I - (1 - eps) n n^T (Sec. 3.1) */
-    GICP_REG_ELLIPSE = 2    /* covariance divided by its middle eigenvalue (Sec. 3.1) */
+    GICP_REG_PLANE = 1,     /* eigenvalues replaced by (1, 1, eps): I - (1 - eps) n n^T (Sec. 3.1.1) */
+    GICP_REG_ELLIPSE = 2    /* covariance divided by its middle eigenvalue (Sec. 3.1.1) */
 } gicp_reg_mode;
 
 typedef enum gicp_precision {
@@ -107,7 +108,15 @@ enum {
      * into a HIP graph (per batch shape and workspace) and replayed by one
      * graph launch.  Same kernels and results as the default form.  Kernel
      * timing, when enabled, covers the whole replay under group 0. */
-    GICP_FLAG_GRAPH = 4
+    GICP_FLAG_GRAPH = 4,
+    /* Search every correspondence afresh in every iteration.  By default a
+     * point keeps its previous match while it stays within the radius that
+     * match's search certified (no other mean can have become nearer), and a
+     * search starts from the previous match as its first candidate; both
+     * leave the exact nearest mean unchanged, so results are bitwise equal
+     * with and without this flag (it exists to verify that, and costs the
+     * full search in every iteration).  Combines with any form above. */
+    GICP_FLAG_NO_REUSE = 8
 };
 
 /* One problem of a batched registration. */
@@ -167,12 +176,14 @@ int gicp_knn(gicp_ctx* ctx, const float* pts, int64_t n, const float* queries, i
              int k, float cell, float r_max, int32_t* idx, float* d2, void* stream);
 
 /* Per-point covariances of `pts` from their k nearest neighbours, self
- * included (Sec. 3), with scale regularisation `reg_mode` (Sec. 3.1):
+ * included (Sec. 3), with scale regularisation `reg_mode` (Sec. 3.1.1):
  * C = (1/k) sum_j (p_j - mu)(p_j - mu)^T over the neighbours, mu their mean;
  * PLANE: I - (1 - eps) n n^T with n the eigenvector of the smallest
- * eigenvalue; ELLIPSE: C / lambda_mid.  Output covs SoA [6][n] (device).
- * Asynchronous.  `cell` as in gicp_knn.  Returns GICP_E_ARG for null pointers,
- * n < k or k outside [1,64]. */
+ * eigenvalue; ELLIPSE: C / max(lambda_mid, 1e-6 lambda_max) (an all-zero C
+ * stays zero).  Output covs SoA [6][n] (device).  Asynchronous.  `cell` as in
+ * gicp_knn.  Returns GICP_E_ARG for null pointers, n < k or k outside [3,64]
+ * (fewer than 3 neighbours give a covariance of rank 0 or 1, whose
+ * regularised forms would fix an arbitrary direction). */
 int gicp_covariances(gicp_ctx* ctx, const float* pts, int64_t n, int k, float cell,
                      int reg_mode, float eps, float* covs, void* stream);
 
@@ -181,13 +192,39 @@ int gicp_covariances(gicp_ctx* ctx, const float* pts, int64_t n, int k, float ce
  * the 8-NN distance, which synchronises), builds the cell hash table, and
  * applies the target regularisation `reg_mode` (eps as above) once, so that
  * registrations against the map reuse it (Sec. 3: the map's covariances are
- * never recomputed; Sec. 3.1: target Gaussians are regularised for tracking).
+ * never recomputed; Sec. 3.1.1: target Gaussians are regularised for tracking).
  * The inputs may be freed once the stream has passed this call. */
 int gicp_map_build(gicp_ctx* ctx, const float* means, const float* covs, int64_t m,
                    float cell, int reg_mode, float eps, gicp_map** out, void* stream);
 int gicp_map_destroy(gicp_map* map);
 /* Number of Gaussians and cell size of a map. */
 int gicp_map_info(const gicp_map* map, int64_t* m, float* cell);
+
+/* Nearest map mean of each query within r_max: the correspondence search of
+ * the registration (Sec. 3: correspondences come from nearest-neighbour
+ * search; Eq. MLE_for_T pairs each source point with one map Gaussian), run
+ * by the same device code the batched Gauss-Newton iterations use, exposed so
+ * that it can be checked and used on its own.
+ *   queries  SoA [3][nq] (device), points already in the map frame (q = R x + t)
+ *   r_max    gate in metres: a mean is accepted when its key <= fl(r_max * r_max)
+ *   hints    nullable int32 [nq] (device): a map index per query tried as the
+ *            first candidate (typically its previous match; -1 or an index
+ *            outside [0, m): none).  A hint only speeds up the search; the
+ *            result is the exact nearest mean either way.  The first call
+ *            with hints on a map (and the first after gicp_map_insert)
+ *            allocates and fills a 4-byte-per-Gaussian index table.
+ *   idx      int32 [nq] (device): map index (order of gicp_map_build, then of
+ *            the insertions) of the nearest mean by (FP32 key, index) as in
+ *            gicp_knn, or -1 when none lies within the gate
+ *   d2       float [nq] (device): that key, +inf when none
+ *   radius   nullable float [nq] (device): a distance the query can move by
+ *            (strictly less) without any other mean becoming nearer than the
+ *            match, margins for FP32 rounding included -- the bound under
+ *            which the registration keeps a match between iterations;
+ *            -1 when there is no match or no margin
+ * Asynchronous.  GICP_E_ARG for null pointers, nq < 0 or r_max <= 0. */
+int gicp_map_nearest(gicp_ctx* ctx, gicp_map* map, const float* queries, int64_t nq, float r_max,
+                     const int32_t* hints, int32_t* idx, float* d2, float* radius, void* stream);
 
 /* Registers a source cloud against a map by Gauss-Newton on Eq. MLE_for_T.
  *   src        SoA [3][n] source points (device)
@@ -246,8 +283,8 @@ int gicp_profile(gicp_ctx* ctx, int enable);
 int gicp_profile_read(gicp_ctx* ctx, int group, int64_t* launches, double* total_ms, double* units);
 
 /* ------------------------------------------------------------------------
- * Frame preparation and map growth (Sec. 3 system overview; Sec. 3.2
- * Keyframe Selection; Sec. 3.3 Scale Aligning)
+ * Frame preparation and map growth (Sec. 3 system overview; Sec. 3.1.2
+ * Keyframe Selection; Sec. 3.2.1 Scale Aligning)
  * ------------------------------------------------------------------------ */
 
 /* Depth image -> tracking point cloud (Sec. 3, Fig. 2: the depth image is
@@ -264,8 +301,8 @@ int gicp_depth_to_points(gicp_ctx* ctx, const float* depth, int width, int heigh
                          float cy, float voxel, float max_depth, float* out_xyz, int64_t capacity, int64_t* n_out,
                          void* stream);
 
-/* The Gaussians a keyframe adds to the map (Sec. 3.2: only Gaussians that do
- * not overlap the current map; Sec. 3.3: scale aligning Lambda'' = Lambda' /
+/* The Gaussians a keyframe adds to the map (Sec. 3.1.2: only Gaussians that do
+ * not overlap the current map; Sec. 3.2.1: scale aligning Lambda'' = Lambda' /
  * z^p, i.e. C'' = C' / z^(2p) with z the camera-frame depth).  src [3][n] and
  * src_covs [6][n] (device) are the frame's points and regularised
  * covariances in the camera frame; pose (host double[16]) maps camera to map.
@@ -279,7 +316,7 @@ int gicp_keyframe_gaussians(gicp_ctx* ctx, const float* src, const float* src_co
                             const double pose[16], float r_overlap, float p, float* out_means, float* out_covs,
                             int64_t* n_out, double* inlier_ratio, void* stream);
 
-/* Keyframe decision (Sec. 3.2 and Sec. 3.3, Additional Keyframe Selection for
+/* Keyframe decision (Sec. 3.1.2 and Sec. 3.2.2, Additional Keyframe Selection for
  * Mapping): GICP_KEYFRAME when the correspondence ratio is below `threshold`
  * or `since_keyframe` >= max_gap (> 0); otherwise GICP_MAPPING_ONLY when
  * `since_mapping` (frames since the last keyframe of either kind) >=

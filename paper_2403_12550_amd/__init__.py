@@ -14,11 +14,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_GRAPH, FLAG_MULTI_LAUNCH, FLAG_QUEUE, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK,
-                   Params, Problem, Stats)
+from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_GRAPH, FLAG_MULTI_LAUNCH, FLAG_NO_REUSE, FLAG_QUEUE, REG_ELLIPSE,
+                   REG_NONE, REG_PLANE, GICP_OK, Params, Problem, Stats)
 
 __all__ = ["Context", "Map", "Params", "Stats", "Problem", "RegisterResult", "GicpError", "params",
            "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "FLAG_MULTI_LAUNCH", "FLAG_QUEUE", "FLAG_GRAPH",
+           "FLAG_NO_REUSE",
            "to_soa", "lib"]
 
 
@@ -194,6 +195,24 @@ class Context:
         lib().gicp_map_info(h, C.byref(m), C.byref(c))
         return Map(h, int(m.value), float(c.value))
 
+    def map_nearest(self, gmap: Map, queries, r_max: float, hints=None, want_radius: bool = False):
+        """Nearest map mean of each query [3, nq] (map frame) within r_max by the
+        registration's own search: (idx int32 [nq], d2 float32 [nq], radius or None)."""
+        import torch
+        _check_f32_cuda(queries, 3, "queries")
+        nq = queries.shape[1]
+        if hints is not None and (hints.dtype != torch.int32 or not hints.is_cuda or hints.numel() != nq
+                                  or not hints.is_contiguous()):
+            raise ValueError("hints must be a contiguous int32 CUDA tensor of nq entries")
+        idx = torch.empty(nq, dtype=torch.int32, device=queries.device)
+        d2 = torch.empty(nq, dtype=torch.float32, device=queries.device)
+        rad = torch.empty(nq, dtype=torch.float32, device=queries.device) if want_radius else None
+        st = lib().gicp_map_nearest(self.handle, gmap.handle, _ptr(queries), nq, r_max, _ptr(hints), _ptr(idx),
+                                    _ptr(d2), _ptr(rad), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_map_nearest")
+        return idx, d2, rad
+
     def register(self, src, gmap: Map, init_pose, prm: Params | None = None, src_covs=None,
                  src_covs_out=None, raise_on_error: bool = False) -> RegisterResult:
         _check_f32_cuda(src, 3, "src")
@@ -209,6 +228,27 @@ class Context:
                                  C.byref(prm), pose, H, b, _ptr(src_covs_out), C.byref(stats), _stream())
         if st == _abi.GICP_E_ARG or st in (_abi.GICP_E_HIP, _abi.GICP_E_OOM) or (raise_on_error and st != GICP_OK):
             raise GicpError(st, "gicp_register")
+        return RegisterResult(np.array(pose[:]).reshape(4, 4), np.array(H[:]).reshape(6, 6), np.array(b[:]),
+                              stats.iters, stats.n_inliers, stats.cost, bool(stats.converged), st)
+
+    def register_pair(self, src, map_means, map_covs, init_pose, prm: Params | None = None, src_covs=None,
+                      map_cell: float = 0.0) -> RegisterResult:
+        """The problem-statement form: registers src against Gaussians (means
+        [3, m], covs [6, m], used as given) through a transient map."""
+        _check_f32_cuda(src, 3, "src")
+        _check_f32_cuda(map_means, 3, "map_means")
+        _check_f32_cuda(map_covs, 6, "map_covs")
+        if src_covs is not None:
+            _check_f32_cuda(src_covs, 6, "src_covs")
+        prm = prm or params()
+        init = _abi.D16(*np.asarray(init_pose, np.float64).reshape(16))
+        pose, H, b = _abi.D16(), _abi.D36(), _abi.D6()
+        stats = Stats()
+        st = lib().gicp_register_pair(self.handle, _ptr(src), _ptr(src_covs), src.shape[1], _ptr(map_means),
+                                      _ptr(map_covs), map_means.shape[1], map_cell, init, C.byref(prm), pose, H, b,
+                                      C.byref(stats), _stream())
+        if st in (_abi.GICP_E_ARG, _abi.GICP_E_HIP, _abi.GICP_E_OOM):
+            raise GicpError(st, "gicp_register_pair")
         return RegisterResult(np.array(pose[:]).reshape(4, 4), np.array(H[:]).reshape(6, 6), np.array(b[:]),
                               stats.iters, stats.n_inliers, stats.cost, bool(stats.converged), st)
 

@@ -31,6 +31,7 @@ class Params(C.Structure):
 FLAG_MULTI_LAUNCH = 1
 FLAG_QUEUE = 2
 FLAG_GRAPH = 4
+FLAG_NO_REUSE = 8
 
 
 class Problem(C.Structure):
@@ -87,6 +88,7 @@ SIGNATURES = {
     "gicp_map_build": (C.c_int, [P, P, P, I64, C.c_float, C.c_int, C.c_float, C.POINTER(P), P]),
     "gicp_map_destroy": (C.c_int, [P]),
     "gicp_map_info": (C.c_int, [P, C.POINTER(I64), C.POINTER(C.c_float)]),
+    "gicp_map_nearest": (C.c_int, [P, P, P, I64, C.c_float, P, P, P, P, P]),
     "gicp_register": (C.c_int, [P, P, P, I64, P, D16, C.POINTER(Params), D16, D36, D6, P,
                                 C.POINTER(Stats), P]),
     "gicp_register_pair": (C.c_int, [P, P, P, I64, P, P, I64, C.c_float, D16, C.POINTER(Params), D16, D36,

@@ -21,7 +21,10 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
-    # packed FP32 instructions stay off (the compiler would otherwise form them)
+    # packed FP32 instructions stay off in the device code (without this flag
+    # hipcc -O3 forms v_pk_fma_f32 / v_pk_add_f32 from plain float code for
+    # gfx950; with it, none: checked on the assembly of a float2 kernel).  The
+    # host pass, which has no such feature, warns that it ignores the flag.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # fuse multiply-adds only within one expression, so that the same source
     # expression rounds the same way in every kernel that inlines it

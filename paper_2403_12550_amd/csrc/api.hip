@@ -131,6 +131,8 @@ struct gicp_map {
     float4* spts2 = nullptr;         // spare arrays of the same capacity (merge target of gicp_map_insert)
     float4* scov2 = nullptr;
     uint32_t* keys2 = nullptr;
+    int32_t* inv = nullptr;          // [m] index -> sorted position, built on demand (hinted queries)
+    bool inv_ok = false;
 };
 
 namespace {
@@ -312,7 +314,11 @@ void ensure_states(gicp_ctx* c, int n) {
     c->state_cap = cap;
 }
 
+// neighbour counts: any k in [1, 64] for a search; at least 3 for a
+// covariance (with fewer neighbours it has rank 0 or 1, and a regularised
+// form would fix an arbitrary direction)
 bool valid_k(int k) { return k >= 1 && k <= 64; }
+bool valid_cov_k(int k) { return k >= 3 && k <= 64; }
 bool valid_mode(int m) { return m == GICP_REG_NONE || m == GICP_REG_PLANE || m == GICP_REG_ELLIPSE; }
 
 }  // namespace
@@ -457,7 +463,7 @@ int gicp_knn(gicp_ctx* c, const float* pts, int64_t n, const float* queries, int
 
 int gicp_covariances(gicp_ctx* c, const float* pts, int64_t n, int k, float cell, int reg_mode, float eps,
                      float* covs, void* stream) {
-    if (!c || !pts || !covs || !valid_k(k) || n < k || !valid_mode(reg_mode) || n >= (1ll << 31))
+    if (!c || !pts || !covs || !valid_cov_k(k) || n < k || !valid_mode(reg_mode) || n >= (1ll << 31))
         return GICP_E_ARG;
     try {
         check(hipSetDevice(c->device));
@@ -520,6 +526,7 @@ int gicp_map_destroy(gicp_map* mp) {
     if (mp->spts2) (void)hipFree(mp->spts2);
     if (mp->scov2) (void)hipFree(mp->scov2);
     if (mp->keys2) (void)hipFree(mp->keys2);
+    if (mp->inv) (void)hipFree(mp->inv);
     delete mp;
     return GICP_OK;
 }
@@ -552,7 +559,7 @@ MapView map_view(const gicp_map* map, const gicp_params* prm) {
 
 bool valid_params(const gicp_params* prm) {
     return prm && prm->max_it >= 0 && prm->r_max > 0.f && prm->precision >= 0 && prm->precision <= 2 &&
-           (prm->flags & ~(GICP_FLAG_MULTI_LAUNCH | GICP_FLAG_QUEUE | GICP_FLAG_GRAPH)) == 0;
+           (prm->flags & ~(GICP_FLAG_MULTI_LAUNCH | GICP_FLAG_QUEUE | GICP_FLAG_GRAPH | GICP_FLAG_NO_REUSE)) == 0;
 }
 
 // Graph of the max_it batched iterations for this batch shape and these
@@ -728,6 +735,8 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         pd.n = P.n;
         pd.nchunks = (int32_t)((P.n + kChunk - 1) / kChunk);
         pd.part0 = (int32_t)chunks;
+        pd.fresh = (prm->flags & GICP_FLAG_NO_REUSE) ? 1 : 0;
+        pd.pad_ = 0;
         pd.map = map_view(P.map, prm);
         pd.st = c->d_state + p;
         chunks += pd.nchunks;
@@ -862,7 +871,7 @@ int gicp_register(gicp_ctx* c, const float* src, const float* src_covs, int64_t 
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (!c || !src || !map || !init_pose || !prm || !pose || !H || !b || n < 1 || n >= (1ll << 31))
         return GICP_E_ARG;
-    if (!src_covs && (!valid_k(prm->k) || n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
+    if (!src_covs && (!valid_cov_k(prm->k) || n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
     if (!valid_params(prm)) return GICP_E_ARG;
     if ((n + kChunk - 1) / kChunk >= (1ll << kChunkBits)) return GICP_E_ARG;
     gicp_problem P;
@@ -892,7 +901,7 @@ int gicp_register_batch(gicp_ctx* c, int nprob, const gicp_problem* probs, const
         const gicp_problem& P = probs[p];
         if (!P.src || !P.map || P.n < 1 || P.n >= (1ll << 31)) return GICP_E_ARG;
         if ((P.n + kChunk - 1) / kChunk >= (1ll << kChunkBits)) return GICP_E_ARG;
-        if (!P.src_covs && (!valid_k(prm->k) || P.n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
+        if (!P.src_covs && (!valid_cov_k(prm->k) || P.n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
     }
     std::vector<gicp_stats> st(nprob);
     try {
@@ -917,6 +926,32 @@ int gicp_register_pair(gicp_ctx* c, const float* src, const float* src_covs, int
     st = gicp_register(c, src, src_covs, n, mp, init_pose, prm, pose, H, b, nullptr, stats, stream);
     gicp_map_destroy(mp);
     return st;
+}
+
+int gicp_map_nearest(gicp_ctx* c, gicp_map* mp, const float* queries, int64_t nq, float r_max,
+                     const int32_t* hints, int32_t* idx, float* d2, float* radius, void* stream) {
+    if (!c || !mp || nq < 0 || !(r_max > 0.f) || !std::isfinite(r_max) || nq >= (1ll << 31)) return GICP_E_ARG;
+    if (nq > 0 && (!queries || !idx || !d2)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int32_t* inv = nullptr;
+        if (hints && nq > 0) {
+            if (!mp->inv) check(hipMalloc(&mp->inv, (size_t)std::max<int64_t>(mp->m, 1) * sizeof(int32_t)));
+            if (!mp->inv_ok) {
+                check(launch_map_inverse(mp->spts, mp->m, mp->inv, s));
+                mp->inv_ok = true;
+            }
+            inv = mp->inv;
+        }
+        gicp_params prm;
+        gicp_params_default(&prm);
+        prm.r_max = r_max;
+        check(launch_map_nearest(map_view(mp, &prm), queries, nq, hints, inv, idx, d2, radius, s));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
 }
 
 int gicp_profile(gicp_ctx* c, int enable) {
@@ -1231,6 +1266,12 @@ int gicp_map_insert(gicp_ctx* c, gicp_map* mp, const float* means, const float* 
         mp->mask = tcap - 1;
         mp->m = total;
         mp->cap = cap;
+        if (mp->inv) {
+            check(hipStreamSynchronize(s));
+            (void)hipFree(mp->inv);
+            mp->inv = nullptr;
+        }
+        mp->inv_ok = false;
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);

@@ -298,8 +298,9 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     const MapView& map = P.map;
     // the previous iteration's match stands while q stays within the radius
     // its search certified (the nearest mean cannot have changed); otherwise
-    // search again
-    const int32_t hint = gload((const int32_t*)P.nn_prev, i);
+    // search again, starting from that match (unless every search is to
+    // start afresh)
+    const int32_t hint = P.fresh ? -1 : gload((const int32_t*)P.nn_prev, i);
     bool reuse = false;
     if (hint >= 0) {
         const float4 cq = gload((const float4*)P.nn_cache, i);
@@ -798,7 +799,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev*
 }
 
 // ---------------------------------------------------------------------------
-// Keyframe Gaussians (Sec. 3.2, Keyframe Selection; Sec. 3.3, Scale Aligning)
+// Keyframe Gaussians (Sec. 3.1.2, Keyframe Selection; Sec. 3.2.1, Scale Aligning)
 // ---------------------------------------------------------------------------
 // keep[i] = 1 when R x_i + t has no map mean within r_max (the point adds a
 // new Gaussian), 0 when it has a correspondence.  kGroup lanes per point.
@@ -813,6 +814,46 @@ __global__ __launch_bounds__(kBlock) void k_overlap(MapView m, const float* __re
     const float qz = T.R[6] * x + T.R[7] * y + T.R[8] * z + T.t[2];
     const int32_t pos = nearest<false>(m, qx, qy, qz, l, -1);
     if (l == 0) keep[i] = pos < 0 ? 1u : 0u;
+}
+
+// Nearest map mean of arbitrary queries by the linearisation's own search
+// (nearest<true, kLinGroup>), with its certified radius: the match, its FP32
+// key and the radius (the query can move by less than it without changing
+// its nearest mean), or -1 / +inf / -1 when no mean lies within the gate.
+__global__ __launch_bounds__(kBlock) void k_map_nearest(MapView m, const float* __restrict__ q, int64_t nq,
+                                                       const int32_t* __restrict__ hints,
+                                                       const int32_t* __restrict__ inv, int32_t* __restrict__ idx,
+                                                       float* __restrict__ d2, float* __restrict__ radius) {
+    constexpr int G = kLinGroup;
+    const int l = threadIdx.x & (G - 1);
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
+    if (i >= nq) return;   // uniform over each lane group
+    const float qx = q[i], qy = q[nq + i], qz = q[2 * nq + i];
+    int32_t hint = -1;
+    if (hints) {
+        const int32_t h = hints[i];
+        if (h >= 0 && h < m.g.n) hint = inv[h];
+    }
+    float fr = -1.f;
+    const int32_t pos = nearest<true, G>(m, qx, qy, qz, l, hint, &fr);
+    if (l == 0) {
+        if (pos >= 0) {
+            const float4 p = gload(m.g.spts, pos);
+            idx[i] = (int32_t)__float_as_uint(p.w);
+            d2[i] = rank_key(qx, qy, qz, p.x, p.y, p.z);
+        } else {
+            idx[i] = -1;
+            d2[i] = __builtin_inff();
+        }
+        if (radius) radius[i] = fr;
+    }
+}
+
+__global__ void k_map_inverse(const float4* __restrict__ spts, int64_t m, int32_t* __restrict__ inv) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t o = __float_as_uint(spts[j].w);
+    if ((int64_t)o < m) inv[o] = (int32_t)j;
 }
 
 // The kept points, scale aligned in the camera frame (C / z^(2p), z the
@@ -940,6 +981,21 @@ hipError_t launch_overlap(const MapView& m, const float* src, int64_t n, const P
     if (n <= 0) return hipSuccess;
     const int per = kBlock / kGroup;
     hipLaunchKernelGGL(k_overlap, dim3((unsigned)((n + per - 1) / per)), dim3(kBlock), 0, s, m, src, n, T, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_nearest(const MapView& m, const float* q, int64_t nq, const int32_t* hints, const int32_t* inv,
+                              int32_t* idx, float* d2, float* radius, hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    const int per = kBlock / kLinGroup;
+    hipLaunchKernelGGL(k_map_nearest, dim3((unsigned)((nq + per - 1) / per)), dim3(kBlock), 0, s, m, q, nq, hints,
+                       inv, idx, d2, radius);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_inverse(const float4* spts, int64_t m, int32_t* inv, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_inverse, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, spts, m, inv);
     return hipGetLastError();
 }
 

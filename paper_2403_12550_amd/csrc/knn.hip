@@ -1,6 +1,6 @@
 // k-nearest-neighbour search over the cell grid, fused with the per-point
 // covariance and its scale regularisation (Sec. 3: covariance of the k nearest
-// neighbours; Sec. 3.1: C = R Lambda^2 R^T, plane and ellipse forms).
+// neighbours; Sec. 3.1.1: C = R Lambda^2 R^T, plane and ellipse forms).
 //
 // A group of four consecutive lanes serves one query: the lanes split the
 // candidates of the 27-cell block evenly, each keeps its own best candidates
@@ -383,7 +383,7 @@ __device__ __forceinline__ void jacobi3(Sym3 a, float lam[3], float V[3][3]) {
     V[2][0] = v20; V[2][1] = v21; V[2][2] = v22;
 }
 
-// Scale regularisation of a raw covariance (Sec. 3.1).  out: xx,xy,xz,yy,yz,zz.
+// Scale regularisation of a raw covariance (Sec. 3.1.1).  out: xx,xy,xz,yy,yz,zz.
 __device__ __forceinline__ void regularise(const Sym3& C, int mode, float eps, float out[6]) {
     if (mode == GICP_REG_NONE) {
         out[0] = C.a00; out[1] = C.a01; out[2] = C.a02; out[3] = C.a11; out[4] = C.a12; out[5] = C.a22;
@@ -543,7 +543,7 @@ __device__ __forceinline__ void push_work(int32_t* work, int64_t n, int which, i
 }
 
 // Gate of the first pass, as a multiple of the cell size: the cell is about
-// 1.1 times the typical k-th neighbour distance, so most points find their k
+// 1.2 times the 75th-percentile k-th neighbour distance, so most points find their k
 // neighbours inside it.
 constexpr float kGateCells = 1.25f;
 
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kRetryThreads) void k_knn_cov_retry(GridView g, Seg
 }
 
 // Regularisation pass, one lane per point in cell order: raw covariance ->
-// scale-regularised covariance (Sec. 3.1), written in the cloud's order and,
+// scale-regularised covariance (Sec. 3.1.1), written in the cloud's order and,
 // when requested, in cell order.
 __global__ __launch_bounds__(kBlock) void k_cov_regularise(GridView g, SegSet S, int mode, float eps,
                                                            const float* __restrict__ raw) {

@@ -132,6 +132,8 @@ struct ProbDev {
     int64_t n;
     int32_t nchunks;      // ceil(n / kChunk)
     int32_t part0;        // first partial / item slot of the problem
+    int32_t fresh;        // 1: search every correspondence afresh (no reuse of the previous match, no hint)
+    int32_t pad_;
     MapView map;
     RegState* st;
 };
@@ -185,6 +187,13 @@ struct Pose64 {
 // keep[i] = 1 when R x_i + t has no map mean within m.r_max.
 hipError_t launch_overlap(const MapView& m, const float* src, int64_t n, const Pose32& T, uint32_t* keep,
                           hipStream_t s);
+// Correspondence search of the batched linearisation for arbitrary queries
+// (map frame, SoA [3][nq]); hints are map indices (inv: index -> sorted
+// position, required with hints); radius nullable.
+hipError_t launch_map_nearest(const MapView& m, const float* q, int64_t nq, const int32_t* hints, const int32_t* inv,
+                              int32_t* idx, float* d2, float* radius, hipStream_t s);
+// inv[index of the point at sorted position j] = j for the m points of a map.
+hipError_t launch_map_inverse(const float4* spts, int64_t m, int32_t* inv, hipStream_t s);
 // Kept points -> map-frame means and scale-aligned, rotated covariances at
 // out[pos[i]] (SoA with stride n).
 hipError_t launch_keyframe_gaussians(const float* src, const float* covs, int64_t n, const uint32_t* keep,

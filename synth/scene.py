@@ -96,10 +96,27 @@ def make_room(seed: int, extent=(4.0, 4.0, 3.0), n_spheres: int = 3,
     return s
 
 
+def _near_wall(rng, ex, ey, half, band):
+    """(x, y) of an object's centre within ``band`` of a random vertical wall
+    (its half-size ``half`` [2] keeps it inside the room)."""
+    w = rng.integers(0, 4)
+    off = rng.uniform(0.02, band)
+    if w < 2:
+        x = rng.uniform(half[0] + 0.05, ex - half[0] - 0.05)
+        y = half[1] + off if w == 0 else ey - half[1] - off
+    else:
+        y = rng.uniform(half[1] + 0.05, ey - half[1] - 0.05)
+        x = half[0] + off if w == 2 else ex - half[0] - off
+    return x, y
+
+
 def make_cluttered_room(seed: int, keep_clear: np.ndarray, extent=(4.0, 4.0, 3.0),
-                        n_boxes: int = 20, n_spheres: int = 20, clearance: float = 0.3) -> Scene:
+                        n_boxes: int = 20, n_spheres: int = 20, clearance: float = 0.3,
+                        wall_band: float | None = None) -> Scene:
     """Room with axis-aligned boxes (sides U(0.1,0.6) m) and spheres (r U(0.1,0.4) m),
-    each kept at least ``clearance`` from every point of ``keep_clear`` (the camera path)."""
+    each kept at least ``clearance`` from every point of ``keep_clear`` (the camera path).
+    Objects are placed uniformly in the room, or, with ``wall_band``, within that
+    distance of a random vertical wall (like furniture along the walls)."""
     rng = np.random.default_rng(seed)
     ex, ey, ez = extent
     s = Scene(extent=tuple(extent))
@@ -109,6 +126,9 @@ def make_cluttered_room(seed: int, keep_clear: np.ndarray, extent=(4.0, 4.0, 3.0
     while placed < n_boxes:
         side = rng.uniform(0.1, 0.6, size=3)
         lo = rng.uniform([0.05, 0.05, 0.0], [ex - side[0] - 0.05, ey - side[1] - 0.05, ez - side[2] - 0.05])
+        if wall_band is not None:
+            x, y = _near_wall(rng, ex, ey, side[:2] / 2, wall_band)
+            lo[:2] = [x - side[0] / 2, y - side[1] / 2]
         hi = lo + side
         # distance from camera path to the box
         d = np.linalg.norm(np.maximum(np.maximum(lo - keep, keep - hi), 0.0), axis=1)
@@ -121,6 +141,8 @@ def make_cluttered_room(seed: int, keep_clear: np.ndarray, extent=(4.0, 4.0, 3.0
         r = rng.uniform(0.1, 0.4)
         m = r + 0.05
         c = rng.uniform([m, m, m], [ex - m, ey - m, ez - m])
+        if wall_band is not None:
+            c[:2] = _near_wall(rng, ex, ey, np.array([r, r]), wall_band)
         d = np.linalg.norm(keep - c, axis=1) - r
         if d.min() < clearance:
             continue

@@ -17,17 +17,29 @@ def _look_rotation(yaw, pitch):
 
 
 def smooth_trajectory(seed: int, n_frames: int = 100, extent=(4.0, 4.0, 3.0),
-                      max_step_m: float = 0.02, max_step_deg: float = 1.0, n_ctrl: int = 8):
+                      max_step_m: float = 0.02, max_step_deg: float = 1.0, n_ctrl: int = 8,
+                      inward: bool = False, ring: float = 1.5):
     """Camera poses T_wc [n,4,4] along a periodic cubic spline through random control
     points (position, yaw, pitch), re-timed so that no frame-to-frame step exceeds
-    ``max_step_m`` of translation or ``max_step_deg`` of rotation."""
+    ``max_step_m`` of translation or ``max_step_deg`` of rotation.
+
+    Default: control points within 0.75 m of the room centre, the view turning
+    outward (yaw advancing around the loop).  ``inward``: control points on a
+    ring of radius ``ring`` (+-0.2 m) around the centre, the camera facing the
+    centre (+-0.35 rad of yaw wobble), so that every view holds the clutter of
+    the room's middle in front of the far wall."""
     rng = np.random.default_rng(seed)
     ex, ey, ez = extent
     c = np.array([ex / 2, ey / 2, 1.5])
-    P = c + rng.uniform([-0.75, -0.75, -0.3], [0.75, 0.75, 0.3], size=(n_ctrl, 3))
+    if inward:
+        phi = rng.uniform(0, 2 * np.pi) + 2 * np.pi * np.arange(n_ctrl) / n_ctrl
+        rad = ring + rng.uniform(-0.2, 0.2, size=n_ctrl)
+        P = c + np.stack([rad * np.cos(phi), rad * np.sin(phi), rng.uniform(-0.3, 0.3, size=n_ctrl)], 1)
+    else:
+        P = c + rng.uniform([-0.75, -0.75, -0.3], [0.75, 0.75, 0.3], size=(n_ctrl, 3))
     yaw0 = rng.uniform(0, 2 * np.pi)
     yaw_rate = 2 * np.pi / n_ctrl * rng.uniform(0.5, 1.0)
-    wobble = np.append(rng.uniform(-0.4, 0.4, size=n_ctrl), 0.0)
+    wobble = np.append(rng.uniform(-0.35, 0.35, size=n_ctrl) if inward else rng.uniform(-0.4, 0.4, size=n_ctrl), 0.0)
     wobble[-1] = wobble[0]
     pitch = np.append(rng.uniform(-0.25, 0.1, size=n_ctrl), 0.0)
     pitch[-1] = pitch[0]
@@ -39,8 +51,13 @@ def smooth_trajectory(seed: int, n_frames: int = 100, extent=(4.0, 4.0, 3.0),
 
     def pose(s):
         T = np.eye(4)
-        T[:3, :3] = _look_rotation(yaw0 + yaw_rate * s + sy(s), sq(s))
-        T[:3, 3] = sp(s)
+        p = sp(s)
+        if inward:
+            yaw = np.arctan2(c[1] - p[1], c[0] - p[0]) + sy(s)
+        else:
+            yaw = yaw0 + yaw_rate * s + sy(s)
+        T[:3, :3] = _look_rotation(yaw, sq(s))
+        T[:3, 3] = p
         return T
 
     # re-time: walk along the periodic spline in small increments and emit a

@@ -64,11 +64,12 @@ class C2Sequence:
     """Frame-to-map tracking workload.  Frames are rendered lazily and cached."""
 
     def __init__(self, n_frames=100, scene_seed=10, traj_seed=11, map_seed=12,
-                 map_size=1_000_000, voxel=0.02, K=C2_INTRINSICS, extent=(5.5, 5.0, 3.0)):
+                 map_size=1_000_000, voxel=0.02, K=C2_INTRINSICS, extent=(5.5, 5.0, 3.0), inward=False,
+                 wall_band=None):
         self.K = K
         self.voxel = voxel
-        self.poses = smooth_trajectory(traj_seed, n_frames, extent=extent)
-        self.scene = make_cluttered_room(scene_seed, self.poses[:, :3, 3], extent=extent)
+        self.poses = smooth_trajectory(traj_seed, n_frames, extent=extent, inward=inward)
+        self.scene = make_cluttered_room(scene_seed, self.poses[:, :3, 3], extent=extent, wall_band=wall_band)
         mp, mn = sample_surface(self.scene, map_size, map_seed, noise_sigma=0.001)
         self.map_means = mp.astype(np.float32)
         self.map_cov_raw = disc_covariances(mn, map_seed + 1).astype(np.float32)
@@ -92,7 +93,9 @@ class C2Sequence:
         return corrupt_depth(d, 100 + i, 200 + i).astype(np.float32)
 
     def prefetch(self, indices, workers: int = 8):
-        """Render several frames in parallel worker processes (fork)."""
+        """Render several frames in parallel worker processes (fork).  Call it
+        before the process initialises the GPU runtime: a forked copy of a
+        process with an initialised GPU runtime is not safe to run."""
         import concurrent.futures as cf
         import multiprocessing as mp
         todo = [i for i in indices if i not in self._frames]

@@ -7,8 +7,6 @@ benchmark times (50 frames per batched call with graph-replayed iterations; all
 Bars as at the small sizes: neighbour indices and FP32 keys bit-exact;
 covariances within 1e-5 relative (Frobenius) where the normal is determined;
 poses within 1e-5 rad and 1e-5 m of the FP64 oracle."""
-import os
-
 import numpy as np
 import pytest
 
@@ -17,6 +15,8 @@ from oracle import covariance as oc
 from oracle import gicp as og
 from oracle import knn as ok
 from oracle import se3
+
+import covcheck
 
 pytestmark = pytest.mark.gpu
 
@@ -52,8 +52,8 @@ def c2(g, ctx):
     device and the map built as the benchmark builds it."""
     import torch
     _say("c2 workload")
+    # (the frames were rendered at collection time, before the GPU was initialised)
     seq = synth.c2_sequence(n_frames=100, map_size=1_000_000)
-    seq.prefetch(range(BATCH), workers=max(1, min(16, len(os.sched_getaffinity(0)))))
     frames = [g.to_soa(seq.frame(i)) for i in range(BATCH)]
     gm = ctx.map_build(g.to_soa(seq.map_means), g.to_soa(seq.map_cov_raw), cell=0.03, reg_mode=g.REG_PLANE,
                        eps=1e-3)
@@ -112,24 +112,85 @@ def test_c2_frame_to_map_nearest_sampled(g, ctx, c2):
     assert (d2.cpu().numpy()[s].view(np.uint32) == ek.view(np.uint32)).all()
 
 
-def test_c2_frame_covariances_sampled(g, ctx, c2):
-    """Plane-regularised k = 20 covariances of a whole frame; 3000 sampled rows
-    against the oracle's neighbourhood covariance and regularisation."""
+@pytest.mark.parametrize("offset", [False, True])
+def test_c2_map_nearest_sampled(g, ctx, c2, offset):
+    """The registration's own correspondence search (gicp_map_nearest) for a
+    whole frame against the 1M-Gaussian map handle, at the true pose and at a
+    pose 5 cm / 2 deg off; 5000 sampled rows bit-exact against the oracle's
+    gated (FP32 key, index) 1-NN, without and with hints; the certified radius
+    of 2000 sampled rows holds under displacement."""
+    import torch
+    seq, _, gm = c2
+    p = seq.frame(49)
+    T = seq.poses[49]
+    if offset:
+        T = T @ synth.random_offset(np.random.default_rng(7), 2.0, 0.05, exact=True)
+    q = (p.astype(np.float64) @ T[:3, :3].T + T[:3, 3]).astype(np.float32)
+    _say("c2 map_nearest", q.shape[0], offset)
+    Q = g.to_soa(q)
+    idx, d2, rad = ctx.map_nearest(gm, Q, R_MAX, want_radius=True)
+    s = _sample(q.shape[0], 5000, 4)
+    ei, ek = ok.knn_kdtree(seq.map_means, q[s], 1)
+    gate = np.float32(np.float32(R_MAX) * np.float32(R_MAX))
+    far = ek[:, 0] > gate
+    ei[far, 0] = ok.INT_SENTINEL
+    ek[far, 0] = np.inf
+    assert (idx.cpu().numpy()[s] == ei[:, 0]).all()
+    assert (d2.cpu().numpy()[s].view(np.uint32) == ek[:, 0].view(np.uint32)).all()
+    full = idx.cpu().numpy()
+    rng = np.random.default_rng(8)
+    for name, h in (("previous", np.where(full >= 0, full, -1)),
+                    ("random", rng.integers(0, gm.m, q.shape[0])),
+                    ("invalid", np.full(q.shape[0], gm.m + 1))):
+        hi, hd, _ = ctx.map_nearest(gm, Q, R_MAX, hints=torch.from_numpy(h.astype(np.int32)).cuda())
+        assert (hi.cpu().numpy() == full).all(), name
+        assert (hd.cpu().numpy().view(np.uint32) == d2.cpu().numpy().view(np.uint32)).all(), name
+    r = rad.cpu().numpy()
+    s2 = _sample(q.shape[0], 2000, 5)
+    s2 = s2[r[s2] > 0]
+    assert s2.size > 500
+    d = rng.standard_normal((s2.size, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    qq = (q[s2].astype(np.float64) + d * (0.999 * r[s2, None].astype(np.float64))).astype(np.float32)
+    mi, _ = ok.knn_kdtree(seq.map_means, qq, 1)
+    assert (mi[:, 0] == full[s2]).all()
+
+
+def test_c2_no_reuse_bitwise(g, ctx, c2):
+    """50 frames in the timed (graph-replayed batched) form, with and without
+    a fresh search for every point in every iteration: identical outputs."""
+    seq, frames, gm = c2
+    src_cell = ctx.estimate_cell(frames[0], 20)
+    items = [(frames[i], None, gm, _init(seq, i)) for i in range(BATCH)]
+    out = []
+    for flags in (g.FLAG_GRAPH, g.FLAG_GRAPH | g.FLAG_NO_REUSE):
+        _say("c2 no_reuse", flags)
+        prm = g.params(k=20, eps=1e-3, r_max=R_MAX, max_it=MAX_IT, conv_rot=CONV, conv_trans=CONV,
+                       reg_mode=g.REG_PLANE, cell_src=src_cell, flags=flags)
+        out.append(ctx.register_batch(items, prm))
+    for a, b in zip(*out):
+        assert a.status == 0 and np.array_equal(a.pose, b.pose) and np.array_equal(a.H, b.H)
+        assert np.array_equal(a.b, b.b) and a.iters == b.iters and a.n_inliers == b.n_inliers
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_c2_frame_covariances_sampled(g, ctx, c2, mode):
+    """Plane- and ellipse-regularised k = 20 covariances of a whole frame; 3000
+    sampled rows against the oracle's neighbourhood covariance and
+    regularisation, every sampled row checked (tests/covcheck.py)."""
     seq, frames, _ = c2
     p = seq.frame(0)
-    _say("c2 covariances", p.shape[0])
-    got = ctx.covariances(frames[0], 20, reg_mode=g.REG_PLANE, eps=1e-3).cpu().numpy().T.astype(np.float64)
+    _say("c2 covariances", p.shape[0], mode)
+    got = ctx.covariances(frames[0], 20, reg_mode=mode, eps=1e-3).cpu().numpy().T.astype(np.float64)
     s = _sample(p.shape[0], 3000, 3)
     nbr, _ = ok.knn_kdtree(p, p[s], 20)
     Craw = oc.neighbourhood_covariance(p, nbr)
-    exp = oc.to6(oc.regularise(Craw, oc.REG_PLANE, 1e-3))
-    A, B = oc.from6(got[s]), oc.from6(exp)
-    err = np.linalg.norm(A - B, axis=(1, 2)) / np.linalg.norm(B, axis=(1, 2))
-    well = oc.eigen_gap(Craw) >= GAP_GATE
-    assert well.mean() > 0.9
-    assert err[well].max() < 1e-5, err[well].max()
-    lam = np.linalg.eigvalsh(oc.from6(got))
-    assert np.allclose(lam, [1e-3, 1, 1], atol=2e-6)
+    if mode == 1:
+        stats = covcheck.check_plane(got[s], Craw)
+        assert stats[1] > 0.9
+    else:
+        stats = covcheck.check_ellipse(got[s], Craw)
+    _say("  ", stats)
 
 
 def test_c2_batched_graph_poses_vs_oracle(g, ctx, c2):
@@ -204,3 +265,18 @@ def _c4_oracle(p):
         _C4_ORACLE[key] = og.register(p.src, cs, p.tgt, ct, p.init, r_max=0.1, max_it=30, conv_rot=CONV,
                                       conv_trans=CONV)
     return _C4_ORACLE[key]
+
+
+def test_c4_no_reuse_bitwise(g, ctx, c4):
+    """All 64 problems in one batched call, with and without a fresh search
+    for every point in every iteration: identical outputs."""
+    _, items = c4
+    out = []
+    for flags in (0, g.FLAG_NO_REUSE):
+        _say("c4 no_reuse", flags)
+        prm = g.params(k=20, eps=1e-3, r_max=0.1, max_it=30, conv_rot=CONV, conv_trans=CONV,
+                       reg_mode=g.REG_PLANE, flags=flags)
+        out.append(ctx.register_batch(items, prm))
+    for a, b in zip(*out):
+        assert a.status == 0 and np.array_equal(a.pose, b.pose) and np.array_equal(a.H, b.H)
+        assert np.array_equal(a.b, b.b) and a.iters == b.iters and a.n_inliers == b.n_inliers

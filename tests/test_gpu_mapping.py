@@ -99,15 +99,19 @@ def test_keyframe_gaussians_parity(env):
     assert 0.2 < r_o < 0.95
     assert abs(ratio - r_o) * len(src) <= 2
     mg, cg = means.cpu().numpy().T.astype(np.float64), covs.cpu().numpy().T.astype(np.float64)
+    # a point at the overlap boundary may be decided differently (FP32 test):
+    # the kept sets are matched by position, and every matched Gaussian's mean
+    # and covariance compared; at most two points may be unmatched per side
+    from scipy.spatial import cKDTree
+    d, j = cKDTree(m_o).query(mg)
+    matched = d < 1e-5
+    assert matched.sum() >= len(mg) - 2 and matched.sum() >= len(m_o) - 2
     if len(mg) == len(m_o):
-        assert np.abs(mg - m_o).max() <= 1e-6 * max(1.0, np.abs(m_o).max())
-        rel = np.linalg.norm(cg - c_o, axis=1) / np.linalg.norm(c_o, axis=1)
-        assert rel.max() < 1e-5
-    else:
-        # a boundary point decided differently: compare the common points by position
-        from scipy.spatial import cKDTree
-        d, j = cKDTree(m_o).query(mg)
-        assert (d < 1e-5).sum() >= len(mg) - 2
+        assert matched.all() and (j == np.arange(len(m_o))).all()
+    assert np.abs(mg[matched] - m_o[j[matched]]).max() <= 1e-6 * max(1.0, np.abs(m_o).max())
+    rel = np.linalg.norm(cg[matched] - c_o[j[matched]], axis=1) / np.linalg.norm(c_o[j[matched]], axis=1)
+    _say("  kept", len(mg), len(m_o), "max rel cov", rel.max())
+    assert rel.max() < 1e-5
 
 
 def test_map_insert_equals_build(env):
