@@ -60,7 +60,8 @@ typedef enum gicp_status {
     GICP_E_DEGENERATE = 4,  /* Cholesky of H failed: a pivot <= 1e-12 * max(diag H) */
     GICP_E_OOM = 5,         /* device allocation failed */
     GICP_E_HIP = 6,         /* a HIP runtime call failed (code in gicp_stats.hip_error) */
-    GICP_E_INEXACT = 7      /* k-NN could not be proven exact (never expected; see gicp_knn) */
+    GICP_E_INEXACT = 7,     /* k-NN could not be proven exact (never expected; see gicp_knn) */
+    GICP_E_TOO_LARGE = 8    /* input larger than the fixed workspace of gicp_covariances_noalloc */
 } gicp_status;
 
 typedef enum gicp_reg_mode {
@@ -186,6 +187,23 @@ int gicp_knn(gicp_ctx* ctx, const float* pts, int64_t n, const float* queries, i
  * regularised forms would fix an arbitrary direction). */
 int gicp_covariances(gicp_ctx* ctx, const float* pts, int64_t n, int k, float cell,
                      int reg_mode, float eps, float* covs, void* stream);
+
+/* gicp_covariances for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * gicp_covariances, but every workspace lives in one fixed device array of
+ * the library (12.5 MiB per GPU, reserved when the library is loaded and held
+ * until the process ends), and the call allocates nothing.
+ *   n must not exceed GICP_NOALLOC_MAX_POINTS: larger inputs return
+ *   GICP_E_TOO_LARGE.  cell <= 0 estimates the cell size, which synchronises
+ *   the stream (and so cannot be captured); give cell > 0 for capture.
+ * Every call on a GPU uses that GPU's one array, whatever the context: calls
+ * that overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller.  The array keeps the last call's contents; each
+ * call clears what it needs. */
+#define GICP_NOALLOC_MAX_POINTS 131072
+int gicp_covariances_noalloc(gicp_ctx* ctx, const float* pts, int64_t n, int k, float cell, int reg_mode,
+                             float eps, float* covs, void* stream);
 
 /* Builds a map handle from Gaussians (means SoA [3][m], covs SoA [6][m],
  * device): sorts them into grid cells of size `cell` (<= 0: estimated from

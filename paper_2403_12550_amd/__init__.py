@@ -182,6 +182,20 @@ class Context:
             raise GicpError(st, "gicp_covariances")
         return covs
 
+    def covariances_noalloc(self, pts, k: int = 20, cell: float = 0.0, reg_mode: int = REG_PLANE,
+                            eps: float = 1e-3, out=None):
+        """covariances() through the entry point that allocates nothing (fixed
+        per-GPU workspace, at most NOALLOC_MAX_POINTS points)."""
+        import torch
+        _check_f32_cuda(pts, 3, "pts")
+        n = pts.shape[1]
+        covs = torch.empty((6, n), dtype=torch.float32, device=pts.device) if out is None else out
+        st = lib().gicp_covariances_noalloc(self.handle, _ptr(pts), n, k, cell, reg_mode, eps, _ptr(covs),
+                                            _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_covariances_noalloc")
+        return covs
+
     def map_build(self, means, covs, cell: float = 0.0, reg_mode: int = REG_NONE, eps: float = 1e-3) -> Map:
         _check_f32_cuda(means, 3, "means")
         _check_f32_cuda(covs, 6, "covs")

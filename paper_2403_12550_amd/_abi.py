@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgicp.so")
 
 GICP_OK, GICP_E_ARG, GICP_E_NONFINITE, GICP_E_NO_CORR, GICP_E_DEGENERATE, GICP_E_OOM, GICP_E_HIP, \
-    GICP_E_INEXACT = range(8)
+    GICP_E_INEXACT, GICP_E_TOO_LARGE = range(9)
+NOALLOC_MAX_POINTS = 131072
 REG_NONE, REG_PLANE, REG_ELLIPSE = 0, 1, 2
 ACC_TWOSUM, ACC_FP32, ACC_FP64 = 0, 1, 2
 
@@ -85,6 +86,7 @@ SIGNATURES = {
     "gicp_estimate_cell": (C.c_int, [P, P, I64, C.c_int, C.POINTER(C.c_float), P]),
     "gicp_knn": (C.c_int, [P, P, I64, P, I64, C.c_int, C.c_float, C.c_float, P, P, P]),
     "gicp_covariances": (C.c_int, [P, P, I64, C.c_int, C.c_float, C.c_int, C.c_float, P, P]),
+    "gicp_covariances_noalloc": (C.c_int, [P, P, I64, C.c_int, C.c_float, C.c_int, C.c_float, P, P]),
     "gicp_map_build": (C.c_int, [P, P, P, I64, C.c_float, C.c_int, C.c_float, C.POINTER(P), P]),
     "gicp_map_destroy": (C.c_int, [P]),
     "gicp_map_info": (C.c_int, [P, C.POINTER(I64), C.POINTER(C.c_float)]),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -67,8 +68,15 @@ struct ProfMark {
     int iter;   // Gauss-Newton iteration index (-1: not an iteration)
 };
 
+// Fixed workspace of gicp_covariances_noalloc: one copy per GPU the library
+// runs on, held until the process ends.  Host code never uses this name as an
+// address; it uses the device address looked up once per device below.
+constexpr size_t kNoAllocBytes = 13107200;   // 12.5 MiB: the layout for GICP_NOALLOC_MAX_POINTS fits
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
 struct gicp_ctx {
     int device = 0;
+    void* noalloc = nullptr;         // device address of `scratch` on this context's device
     int* d_err = nullptr;
     int* h_err = nullptr;
     GridBufs grid;
@@ -195,34 +203,50 @@ void reserve_grid(GridBufs& gb, int64_t n) {
 // Builds the cell grid of the clouds of S (total points) into `gb`: keys,
 // radix sort (3 passes for one cloud, 4 when the cloud index is part of the
 // key), cell table and the points gathered into grid order.
-GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const SegSet& S, int64_t total, hipStream_t s,
-                    float4* spts_out = nullptr, uint4* table_out = nullptr, uint32_t* keys_out = nullptr) {
-    uint32_t* ka = ensure<uint32_t>(gb.keys_a, total);
-    uint32_t* va = ensure<uint32_t>(gb.vals_a, total);
-    uint32_t* kb = ensure<uint32_t>(gb.keys_b, total);
-    uint32_t* vb = ensure<uint32_t>(gb.vals_b, total);
-    void* scr = ensure<uint8_t>(gb.scratch, radix_scratch_bytes(total));
-    const uint32_t cap = table_capacity(total);
-    float4* spts = spts_out ? spts_out : ensure<float4>(gb.spts, total);
-    uint4* table = table_out ? table_out : ensure<uint4>(gb.table, cap);
-    const int pm = prof_open(ctx, GICP_PROF_GRID, (double)total, -1, s);
-    check(launch_cell_keys(S, total, ka, va, ctx->d_err, s));
+// Device buffers of one grid build (keys and values ping-pong pairs, radix
+// scratch, gathered points, table of `cap` entries).
+struct GridPtrs {
+    uint32_t *ka, *va, *kb, *vb;
+    void* scr;
+    float4* spts;
+    uint4* table;
+    uint32_t cap;
+};
+
+GridView build_grid_into(gicp_ctx* ctx, const GridPtrs& b, const SegSet& S, int64_t total, hipStream_t s,
+                         uint32_t* keys_out, const uint32_t** sorted_vals, bool timed) {
+    const int pm = timed ? prof_open(ctx, GICP_PROF_GRID, (double)total, -1, s) : -1;
+    check(launch_cell_keys(S, total, b.ka, b.va, ctx->d_err, s));
     uint32_t *ks = nullptr, *vs = nullptr;
-    check(radix_sort(ka, va, kb, vb, total, S.count > 1 ? 4 : 3, scr, s, &ks, &vs));
-    check(launch_table_clear(table, cap, s));
-    check(launch_table_build(ks, vs, total, S, spts, table, cap - 1, s));
+    check(radix_sort(b.ka, b.va, b.kb, b.vb, total, S.count > 1 ? 4 : 3, b.scr, s, &ks, &vs));
+    check(launch_table_clear(b.table, b.cap, s));
+    check(launch_table_build(ks, vs, total, S, b.spts, b.table, b.cap - 1, s));
     if (keys_out) check(hipMemcpyAsync(keys_out, ks, total * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     prof_close(ctx, pm, s);
-    gb.sorted_vals = vs;
+    if (sorted_vals) *sorted_vals = vs;
     GridView g;
-    g.spts = spts;
+    g.spts = b.spts;
     g.skeys = ks;
-    g.table = table;
-    g.mask = cap - 1;
+    g.table = b.table;
+    g.mask = b.cap - 1;
     g.n = (int32_t)total;
     g.h = S.one.h;
     g.inv_h = S.one.inv_h;
     return g;
+}
+
+GridView build_grid(gicp_ctx* ctx, GridBufs& gb, const SegSet& S, int64_t total, hipStream_t s,
+                    float4* spts_out = nullptr, uint4* table_out = nullptr, uint32_t* keys_out = nullptr) {
+    GridPtrs b;
+    b.ka = ensure<uint32_t>(gb.keys_a, total);
+    b.va = ensure<uint32_t>(gb.vals_a, total);
+    b.kb = ensure<uint32_t>(gb.keys_b, total);
+    b.vb = ensure<uint32_t>(gb.vals_b, total);
+    b.scr = ensure<uint8_t>(gb.scratch, radix_scratch_bytes(total));
+    b.cap = table_capacity(total);
+    b.spts = spts_out ? spts_out : ensure<float4>(gb.spts, total);
+    b.table = table_out ? table_out : ensure<uint4>(gb.table, b.cap);
+    return build_grid_into(ctx, b, S, total, s, keys_out, &gb.sorted_vals, true);
 }
 
 SegSet one_cloud(const float* xyz, int64_t n, float h, float* covs = nullptr, float* covs_sorted = nullptr) {
@@ -248,10 +272,12 @@ SegSet one_cloud(const float* xyz, int64_t n, float h, float* covs = nullptr, fl
 constexpr int kEstimateSamples = 256;
 constexpr int64_t kEstimateScan = 16384;
 
+// (dbuf / djobs: device buffers of count * kEstimateSamples floats and count
+// descriptors to use instead of the context's workspace)
 void estimate_cells(gicp_ctx* ctx, int count, const float* const* xyz, const int64_t* n, int k, hipStream_t s,
-                    float* cells) {
+                    float* cells, float* dbuf = nullptr, KthJob* djobs_in = nullptr) {
     if (count <= 0) return;
-    float* d = ensure<float>(ctx->kth, (int64_t)count * kEstimateSamples);
+    float* d = dbuf ? dbuf : ensure<float>(ctx->kth, (int64_t)count * kEstimateSamples);
     if (ctx->h_kth_cap < count) {
         if (ctx->h_kth) check(hipHostFree(ctx->h_kth));
         ctx->h_kth = nullptr;
@@ -274,7 +300,7 @@ void estimate_cells(gicp_ctx* ctx, int count, const float* const* xyz, const int
         const int j = std::max(1, (int)std::lround((double)std::min<int64_t>(k, n[i]) / (double)step));
         ctx->h_jobs[i] = KthJob{xyz[i], n[i], step, j, ns[i]};
     }
-    KthJob* djobs = ensure<KthJob>(ctx->kth_jobs, count);
+    KthJob* djobs = djobs_in ? djobs_in : ensure<KthJob>(ctx->kth_jobs, count);
     check(hipMemcpyAsync(djobs, ctx->h_jobs, count * sizeof(KthJob), hipMemcpyHostToDevice, s));
     check(launch_kth_distance(djobs, count, kEstimateSamples, d, s));
     check(hipMemcpyAsync(ctx->h_kth, d, (size_t)count * kEstimateSamples * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -318,6 +344,74 @@ void ensure_states(gicp_ctx* c, int n) {
 // covariance (with fewer neighbours it has rank 0 or 1, and a regularised
 // form would fix an arbitrary direction)
 bool valid_k(int k) { return k >= 1 && k <= 64; }
+
+// Device address of `scratch` on `device` (current), looked up on the first
+// context created on that device and kept for the life of the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) throw HipError{hipErrorInvalidDevice};
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[device] = p;
+    }
+    return g_noalloc_ptr[device];
+}
+
+// Byte offsets of the workspace of one gicp_covariances call on n points
+// inside the fixed array (each region 256-byte aligned).
+struct NoAllocLayout {
+    size_t ka, va, kb, vb, scr, spts, table, raw, work, kth, jobs, end;
+    uint32_t cap;
+};
+
+NoAllocLayout noalloc_layout(int64_t n) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    NoAllocLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += up(bytes);
+        return at;
+    };
+    L.cap = table_capacity(n);
+    L.ka = take(n * sizeof(uint32_t));
+    L.va = take(n * sizeof(uint32_t));
+    L.kb = take(n * sizeof(uint32_t));
+    L.vb = take(n * sizeof(uint32_t));
+    L.scr = take(radix_scratch_bytes(n));
+    L.spts = take(n * sizeof(float4));
+    L.table = take((size_t)L.cap * sizeof(uint4));
+    L.raw = take(6 * n * sizeof(float));
+    L.work = take(knn_cov_work_ints(n) * sizeof(int32_t));
+    L.kth = take(kEstimateSamples * sizeof(float));
+    L.jobs = take(sizeof(KthJob));
+    L.end = o;
+    return L;
+}
+
+// Cell estimate of one cloud (as estimate_cell) with its device buffers
+// given and host storage on the stack: no allocation.  Synchronises.
+float estimate_cell_fixed(gicp_ctx* ctx, const float* xyz, int64_t n, int k, hipStream_t s, float* d, KthJob* djob) {
+    const int ns = (int)std::min<int64_t>(kEstimateSamples, n);
+    const int64_t step = std::max<int64_t>(1, n / kEstimateScan);
+    const int j = std::max(1, (int)std::lround((double)std::min<int64_t>(k, n) / (double)step));
+    ctx->h_jobs[0] = KthJob{xyz, n, step, j, ns};
+    check(hipMemcpyAsync(djob, ctx->h_jobs, sizeof(KthJob), hipMemcpyHostToDevice, s));
+    check(launch_kth_distance(djob, 1, kEstimateSamples, d, s));
+    check(hipMemcpyAsync(ctx->h_kth, d, kEstimateSamples * sizeof(float), hipMemcpyDeviceToHost, s));
+    check(hipStreamSynchronize(s));
+    float v[kEstimateSamples];
+    std::memcpy(v, ctx->h_kth, ns * sizeof(float));
+    std::sort(v, v + ns);
+    float c = v[(size_t)(0.75 * (ns - 1))] * 1.2f;
+    if (!(c > 1e-6f) || !std::isfinite(c)) c = 1e-3f;
+    return c;
+}
 bool valid_cov_k(int k) { return k >= 3 && k <= 64; }
 bool valid_mode(int m) { return m == GICP_REG_NONE || m == GICP_REG_PLANE || m == GICP_REG_ELLIPSE; }
 
@@ -351,6 +445,7 @@ const char* gicp_strerror(int st) {
         case GICP_E_OOM: return "device out of memory";
         case GICP_E_HIP: return "HIP runtime error";
         case GICP_E_INEXACT: return "k-NN not provably exact";
+        case GICP_E_TOO_LARGE: return "input exceeds the fixed workspace of the no-allocation entry point";
         default: return "unknown status";
     }
 }
@@ -369,6 +464,10 @@ int gicp_create(gicp_ctx** out, int device) {
         check(hipHostMalloc(&c->h_err, 256));
         check(hipHostMalloc(&c->h_kth, kEstimateSamples * sizeof(float)));
         c->h_kth_cap = 1;
+        check(hipHostMalloc(&c->h_jobs, sizeof(KthJob)));
+        c->h_jobs_cap = 1;
+        c->noalloc = noalloc_scratch(device);
+        if (noalloc_layout(GICP_NOALLOC_MAX_POINTS).end > kNoAllocBytes) throw HipError{hipErrorInvalidValue};
         check(hipHostMalloc(&c->h_segs, kMaxSegments * sizeof(Seg)));
         *out = c;
         return GICP_OK;
@@ -477,6 +576,39 @@ int gicp_covariances(gicp_ctx* c, const float* pts, int64_t n, int k, float cell
         check(launch_fill_i32(work, 2, 0, s));
         check(launch_knn_cov(g, S, k, reg_mode, eps, raw, work, s));
         prof_close(c, pm, s);
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
+}
+
+int gicp_covariances_noalloc(gicp_ctx* c, const float* pts, int64_t n, int k, float cell, int reg_mode, float eps,
+                             float* covs, void* stream) {
+    if (!c || !pts || !covs || !valid_cov_k(k) || n < k || !valid_mode(reg_mode)) return GICP_E_ARG;
+    if (n > GICP_NOALLOC_MAX_POINTS) return GICP_E_TOO_LARGE;
+    if (!c->noalloc) return GICP_E_HIP;
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        const NoAllocLayout L = noalloc_layout(n);
+        uint8_t* base = static_cast<uint8_t*>(c->noalloc);
+        const float h = cell > 0.f ? cell
+                                   : estimate_cell_fixed(c, pts, n, k, s, reinterpret_cast<float*>(base + L.kth),
+                                                         reinterpret_cast<KthJob*>(base + L.jobs));
+        const SegSet S = one_cloud(pts, n, h, covs);
+        GridPtrs b;
+        b.ka = reinterpret_cast<uint32_t*>(base + L.ka);
+        b.va = reinterpret_cast<uint32_t*>(base + L.va);
+        b.kb = reinterpret_cast<uint32_t*>(base + L.kb);
+        b.vb = reinterpret_cast<uint32_t*>(base + L.vb);
+        b.scr = base + L.scr;
+        b.spts = reinterpret_cast<float4*>(base + L.spts);
+        b.table = reinterpret_cast<uint4*>(base + L.table);
+        b.cap = L.cap;
+        GridView g = build_grid_into(c, b, S, n, s, nullptr, nullptr, false);
+        int32_t* work = reinterpret_cast<int32_t*>(base + L.work);
+        check(launch_fill_i32(work, 2, 0, s));   // the retry and overflow counters start at zero on every call
+        check(launch_knn_cov(g, S, k, reg_mode, eps, reinterpret_cast<float*>(base + L.raw), work, s));
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);
