@@ -280,6 +280,38 @@ int gicp_register(gicp_ctx* ctx, const float* src, const float* src_covs, int64_
 int gicp_register_batch(gicp_ctx* ctx, int nprob, const gicp_problem* probs, const gicp_params* params,
                         double* poses, double* Hs, double* bs, gicp_stats* stats, void* stream);
 
+/* One frame of a tracked sequence. */
+typedef struct gicp_frame {
+    const float* src;       /* SoA [3][n] frame points in the camera frame (device) */
+    const float* src_covs;  /* SoA [6][n] covariances (device), or NULL: computed */
+    int64_t n;
+} gicp_frame;
+
+/* Motion models of gicp_track: the initial pose of frame i >= 1 is the
+ * estimate of frame i-1 (PREVIOUS), or that estimate moved once more by the
+ * last estimated relative motion, T_{i-1} T_{i-2}^-1 T_{i-1}
+ * (CONSTANT_VELOCITY, from frame 2 on; frame 1 starts from frame 0's
+ * estimate). */
+enum { GICP_MOTION_PREVIOUS = 0, GICP_MOTION_CONSTANT_VELOCITY = 1 };
+
+/* Frame-to-map tracking of a sequence (Sec. 3, Fig. 2: every frame is
+ * registered against the map by G-ICP, Eq. MLE_for_T): the frames are
+ * registered in order, each from an initial pose predicted on the device
+ * from the estimates of the frames before it (`motion`), so that the whole
+ * sequence runs without a host round trip between frames.  Frame 0 starts
+ * from init_pose.  Covariances of frames without src_covs are computed first,
+ * in batched launches (they do not depend on any pose).  Per frame the same
+ * Gauss-Newton iterations as gicp_register (params, GICP_FLAG_GRAPH: each
+ * frame's launches replayed from one captured graph; GICP_FLAG_NO_REUSE as
+ * there).  Outputs (host): poses [nframes][16], Hs [nframes][36],
+ * bs [nframes][6] (each nullable), stats [nframes] (nullable).  A frame whose
+ * registration fails (NO_CORR, DEGENERATE) keeps its last valid iterate, and
+ * the next frames predict from it.  Synchronises the stream once.
+ * GICP_E_ARG for nframes outside [1, 4096], an invalid frame or motion. */
+int gicp_track(gicp_ctx* ctx, int nframes, const gicp_frame* frames, const gicp_map* map,
+               const double init_pose[16], int motion, const gicp_params* params, double* poses, double* Hs,
+               double* bs, gicp_stats* stats, void* stream);
+
 /* The problem statement form: builds a transient map from (map_means,
  * map_covs, m) with cell size `map_cell` (<= 0: estimated) and no target
  * regularisation, registers, and destroys the map. */

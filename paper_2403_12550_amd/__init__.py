@@ -14,12 +14,13 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_GRAPH, FLAG_MULTI_LAUNCH, FLAG_NO_REUSE, FLAG_QUEUE, REG_ELLIPSE,
-                   REG_NONE, REG_PLANE, GICP_OK, Params, Problem, Stats)
+from ._abi import (ACC_FP32, ACC_FP64, ACC_TWOSUM, FLAG_GRAPH, FLAG_MULTI_LAUNCH, FLAG_NO_REUSE, FLAG_QUEUE,
+                   MOTION_CONSTANT_VELOCITY, MOTION_PREVIOUS, REG_ELLIPSE, REG_NONE, REG_PLANE, GICP_OK, Frame, Params,
+                   Problem, Stats)
 
 __all__ = ["Context", "Map", "Params", "Stats", "Problem", "RegisterResult", "GicpError", "params",
            "REG_NONE", "REG_PLANE", "REG_ELLIPSE", "ACC_TWOSUM", "ACC_FP32", "ACC_FP64", "FLAG_MULTI_LAUNCH", "FLAG_QUEUE", "FLAG_GRAPH",
-           "FLAG_NO_REUSE",
+           "FLAG_NO_REUSE", "MOTION_PREVIOUS", "MOTION_CONSTANT_VELOCITY",
            "to_soa", "lib"]
 
 
@@ -315,6 +316,35 @@ class Context:
     @staticmethod
     def keyframe_policy(ratio, since_keyframe, since_mapping, threshold, max_gap=30, mapping_gap=10):
         return int(lib().gicp_keyframe_policy(ratio, since_keyframe, since_mapping, threshold, max_gap, mapping_gap))
+
+    def track(self, frames, gmap: Map, init_pose, motion: int = MOTION_PREVIOUS, prm: Params | None = None,
+              covs=None):
+        """Tracks a sequence: frames [3, n_i] registered in order against gmap,
+        frame 0 from init_pose and every later frame from the pose predicted
+        on the device from the previous estimates.  covs: optional list of
+        [6, n_i] (None entries are computed).  Returns a list of RegisterResult."""
+        prm = prm or params()
+        k = len(frames)
+        arr = (Frame * max(k, 1))()
+        for i, f in enumerate(frames):
+            _check_f32_cuda(f, 3, "frame")
+            cv = None if covs is None else covs[i]
+            if cv is not None:
+                _check_f32_cuda(cv, 6, "covs")
+            arr[i].src = f.data_ptr()
+            arr[i].src_covs = 0 if cv is None else cv.data_ptr()
+            arr[i].n = f.shape[1]
+        init = _abi.D16(*np.asarray(init_pose, np.float64).reshape(16))
+        poses = np.zeros((k, 4, 4))
+        Hs = np.zeros((k, 6, 6))
+        bs = np.zeros((k, 6))
+        stats = np.zeros(k, _STATS_DT)
+        st = lib().gicp_track(self.handle, k, arr, gmap.handle, init, motion, C.byref(prm), poses.ctypes.data,
+                              Hs.ctypes.data, bs.ctypes.data, C.cast(stats.ctypes.data, C.POINTER(Stats)), _stream())
+        if st in (_abi.GICP_E_ARG, _abi.GICP_E_HIP, _abi.GICP_E_OOM):
+            raise GicpError(st, "gicp_track")
+        return [RegisterResult(poses[i], Hs[i], bs[i], it, ni, cost, bool(cv), status)
+                for i, (it, ni, cost, cv, status, _, _) in enumerate(stats.tolist())]
 
     def register_batch(self, problems, prm: Params | None = None):
         """problems: sequence of (src [3,n], src_covs [6,n] or None, Map, init_pose 4x4).

@@ -57,6 +57,17 @@ class Stats(C.Structure):
     ]
 
 
+class Frame(C.Structure):
+    _fields_ = [
+        ("src", C.c_void_p),
+        ("src_covs", C.c_void_p),
+        ("n", C.c_int64),
+    ]
+
+
+MOTION_PREVIOUS, MOTION_CONSTANT_VELOCITY = 0, 1
+
+
 class MlpPair(C.Structure):
     _fields_ = [
         ("src", C.c_void_p),
@@ -93,6 +104,8 @@ SIGNATURES = {
     "gicp_map_nearest": (C.c_int, [P, P, P, I64, C.c_float, P, P, P, P, P]),
     "gicp_register": (C.c_int, [P, P, P, I64, P, D16, C.POINTER(Params), D16, D36, D6, P,
                                 C.POINTER(Stats), P]),
+    "gicp_track": (C.c_int, [P, C.c_int, C.POINTER(Frame), P, D16, C.c_int, C.POINTER(Params), P, P, P,
+                             C.POINTER(Stats), P]),
     "gicp_register_pair": (C.c_int, [P, P, P, I64, P, P, I64, C.c_float, D16, C.POINTER(Params), D16, D36,
                                      D6, C.POINTER(Stats), P]),
     "gicp_register_batch": (C.c_int, [P, C.c_int, C.POINTER(Problem), C.POINTER(Params), P, P, P,

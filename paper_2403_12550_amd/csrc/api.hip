@@ -65,7 +65,8 @@ struct ProfMark {
     int group;
     hipEvent_t a, b;
     double units;
-    int iter;   // Gauss-Newton iteration index (-1: not an iteration)
+    int iter;    // Gauss-Newton iteration index (-1: not an iteration)
+    int frame;   // tracked frame (gicp_track), else -1
 };
 
 // Fixed workspace of gicp_covariances_noalloc: one copy per GPU the library
@@ -87,7 +88,7 @@ struct gicp_ctx {
     ProbDev* h_probs = nullptr;      // pinned [state_cap]
     int state_cap = 0;
     QueueDev* d_queue = nullptr;
-    Buf items, arrive, chunk_prob;
+    Buf items, arrive, chunk_prob, track_counter;
     int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
     int h_kth_cap = 0;   // clouds the pinned estimate buffer holds
@@ -105,9 +106,10 @@ struct gicp_ctx {
     Buf dep_pts, dep_vox, dep_flags, dep_pos, dep_scan, dep_misc, ins_cov;
     // graph-captured Gauss-Newton iterations, keyed by batch shape and workspace
     struct GraphEntry {
-        int nprob, max_it, acc;
+        int kind;   // 0: batched iterations, 1: one tracked frame
+        int nprob, max_it, acc, motion;
         int64_t chunks;
-        const void *probs, *chunk_prob, *part;
+        const void *probs, *chunk_prob, *part, *counter;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -157,9 +159,9 @@ hipEvent_t next_event(gicp_ctx* c) {
 }
 
 // Opens a timed region on stream s (no-op unless profiling); returns its mark index.
-int prof_open(gicp_ctx* c, int group, double units, int iter, hipStream_t s) {
+int prof_open(gicp_ctx* c, int group, double units, int iter, hipStream_t s, int frame = -1) {
     if (!c->prof) return -1;
-    ProfMark m{group, next_event(c), next_event(c), units, iter};
+    ProfMark m{group, next_event(c), next_event(c), units, iter, frame};
     check(hipEventRecord(m.a, s));
     c->marks.push_back(m);
     return (int)c->marks.size() - 1;
@@ -174,6 +176,19 @@ void prof_close(gicp_ctx* c, int mark, hipStream_t s) {
 // `iters_done` were launched but returned at once (converged) and are skipped.
 void prof_collect(gicp_ctx* c, int iters_done) {
     for (const ProfMark& m : c->marks) {
+        if (m.frame >= 0) {
+            // a tracked frame: its launches after convergence did no work; a
+            // graph replay (iter -2) covers all of the frame's iterations
+            const int it = c->h_state[m.frame].iters;
+            if (m.iter >= 0 && m.iter >= it) continue;
+            float ms = 0.f;
+            check(hipEventSynchronize(m.b));
+            check(hipEventElapsedTime(&ms, m.a, m.b));
+            c->launches[m.group] += 1;
+            c->ms[m.group] += ms;
+            c->units[m.group] += m.iter == -2 ? m.units * it : m.units;
+            continue;
+        }
         if (m.iter >= 0 && m.iter >= iters_done) continue;
         float ms = 0.f;
         check(hipEventSynchronize(m.b));
@@ -485,7 +500,7 @@ int gicp_destroy(gicp_ctx* c) {
                    &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
                    &c->nn_prev, &c->nn_cache, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
                    &c->mlp_lpair, &c->dep_pts, &c->dep_vox, &c->dep_flags, &c->dep_pos, &c->dep_scan, &c->dep_misc,
-                   &c->ins_cov, &c->kth_jobs})
+                   &c->ins_cov, &c->kth_jobs, &c->track_counter})
         release(*b);
     for (auto& ge : c->graphs) (void)hipGraphExecDestroy(ge.exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -697,13 +712,13 @@ bool valid_params(const gicp_params* prm) {
 // Graph of the max_it batched iterations for this batch shape and these
 // workspace addresses (captured once on a private stream, then cached).
 constexpr int64_t kGraphBucket = 1024;   // launch grids are padded to a multiple of this many chunks
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxGraphs = 16;
 
 hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int32_t* chunk_prob,
                                double* part) {
     for (auto& e : c->graphs)
-        if (e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc && e.probs == c->d_probs &&
-            e.chunk_prob == chunk_prob && e.part == part)
+        if (e.kind == 0 && e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc &&
+            e.probs == c->d_probs && e.chunk_prob == chunk_prob && e.part == part)
             return e.exec;
     if (!c->capture_stream) check(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = c->capture_stream;
@@ -726,17 +741,59 @@ hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it,
         (void)hipGraphExecDestroy(c->graphs.front().exec);
         c->graphs.erase(c->graphs.begin());
     }
-    c->graphs.push_back({nprob, max_it, acc, grid, c->d_probs, chunk_prob, part, exec});
+    c->graphs.push_back({0, nprob, max_it, acc, 0, grid, c->d_probs, chunk_prob, part, nullptr, exec});
+    return exec;
+}
+
+// Graph of one tracked frame (k_track_begin, then max_it iterations), valid
+// for every frame of a call: which frame runs comes from the device counter.
+hipGraphExec_t track_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int motion, int32_t* counter,
+                           int32_t* chunk_prob, double* part) {
+    for (auto& e : c->graphs)
+        if (e.kind == 1 && e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc &&
+            e.motion == motion && e.probs == c->d_probs && e.chunk_prob == chunk_prob && e.part == part &&
+            e.counter == counter)
+            return e.exec;
+    if (!c->capture_stream) check(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->capture_stream;
+    hipGraph_t graph = nullptr;
+    check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t err = launch_track_begin(c->d_probs, nprob, counter, chunk_prob, grid, motion, cs);
+    for (int it = 0; it < max_it && err == hipSuccess; ++it)
+        err = launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, true, true, cs);
+    const hipError_t end = hipStreamEndCapture(cs, &graph);
+    check(err);
+    check(end);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    check(inst);
+    if (c->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({1, nprob, max_it, acc, motion, grid, c->d_probs, chunk_prob, part, counter, exec});
     return exec;
 }
 
 // Registers nprob problems (validated by the caller).  covs_out[p] (nullable)
 // receives problem p's source covariances when the call computes them.
 // Returns the per-problem statuses in stats (never null here).
-void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm,
-                   float* const* covs_out, double* poses, double* Hs, double* bs, gicp_stats* stats, hipStream_t s) {
-    // 1. source covariances where missing; such problems are then linearised
-    // in their grid-cell order (sorted copies of the points and covariances)
+// Per-problem source arrays after prepare_sources: the covariances the
+// linearisation reads and, for problems whose covariances the call computed,
+// the grid-order copies of points and covariances it walks instead.
+struct Sources {
+    std::vector<const float*> scov;
+    std::vector<const float4*> ssrc;
+    std::vector<const float*> sscov;
+    int32_t* nnprev = nullptr;
+    float4* nncache = nullptr;
+};
+
+// 1. source covariances where missing; such problems are then linearised in
+// their grid-cell order (sorted copies of the points and covariances)
+void prepare_sources(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm,
+                     float* const* covs_out, Sources& out, hipStream_t s) {
     int64_t nsorted = 0, ntot = 0;
     for (int p = 0; p < nprob; ++p) {
         ntot += probs[p].n;
@@ -764,9 +821,14 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         reserve_grid(c->grid, nmax);
         ensure<int32_t>(c->overflow, knn_cov_work_ints(nmax));
     }
-    std::vector<const float*> scov(nprob);
-    std::vector<const float4*> ssrc(nprob, nullptr);
-    std::vector<const float*> sscov(nprob, nullptr);
+    std::vector<const float*>& scov = out.scov;
+    std::vector<const float4*>& ssrc = out.ssrc;
+    std::vector<const float*>& sscov = out.sscov;
+    scov.assign(nprob, nullptr);
+    ssrc.assign(nprob, nullptr);
+    sscov.assign(nprob, nullptr);
+    out.nnprev = nnprev;
+    out.nncache = nncache;
     // problems with caller covariances keep the caller's order
     for (int p = 0; p < nprob; ++p) {
         const gicp_problem& P = probs[p];
@@ -838,8 +900,17 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         if (g1 < todo.size()) check(hipStreamSynchronize(s));   // the staging array is reused
     }
     check(launch_fill_i32(nnprev, ntot, -1, s));
-    // 2. states and problem descriptors
+}
+
+// 2. states and problem descriptors (host copies; the caller uploads them).
+// part0 of problem p is the running chunk count unless shared_partials, where
+// every problem starts at slot 0 (problems that run one after another).
+// Returns the total chunk count (shared: the largest).
+int64_t prepare_states(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm,
+                       const Sources& src, bool shared_partials) {
     ensure_states(c, nprob);
+    int32_t* nnprev = src.nnprev;
+    float4* nncache = src.nncache;
     int64_t chunks = 0;
     for (int p = 0; p < nprob; ++p) {
         const gicp_problem& P = probs[p];
@@ -857,22 +928,58 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         hs.acc = prm->precision;
         ProbDev& pd = c->h_probs[p];
         pd.src = P.src;
-        pd.scov = scov[p];
-        pd.ssrc = ssrc[p];
-        pd.sscov = sscov[p];
+        pd.scov = src.scov[p];
+        pd.ssrc = src.ssrc[p];
+        pd.sscov = src.sscov[p];
         pd.nn_prev = nnprev;
         pd.nn_cache = nncache;
         nnprev += P.n;
         nncache += P.n;
         pd.n = P.n;
         pd.nchunks = (int32_t)((P.n + kChunk - 1) / kChunk);
-        pd.part0 = (int32_t)chunks;
+        pd.part0 = shared_partials ? 0 : (int32_t)chunks;
         pd.fresh = (prm->flags & GICP_FLAG_NO_REUSE) ? 1 : 0;
         pd.pad_ = 0;
         pd.map = map_view(P.map, prm);
         pd.st = c->d_state + p;
-        chunks += pd.nchunks;
+        chunks = shared_partials ? std::max<int64_t>(chunks, pd.nchunks) : chunks + pd.nchunks;
     }
+    return chunks;
+}
+
+// Host outputs of nprob registrations from the downloaded states.
+void write_results(gicp_ctx* c, int nprob, bool nonfinite, bool qerr, double* poses, double* Hs, double* bs,
+                   gicp_stats* stats) {
+    for (int p = 0; p < nprob; ++p) {
+        const RegState& hs = c->h_state[p];
+        if (poses)
+            for (int i = 0; i < 16; ++i) poses[16 * p + i] = hs.pose[i];
+        if (Hs) {
+            int q = 0;
+            for (int i = 0; i < 6; ++i)
+                for (int j = i; j < 6; ++j) {
+                    Hs[36 * p + 6 * i + j] = hs.H[q];
+                    Hs[36 * p + 6 * j + i] = hs.H[q];
+                    ++q;
+                }
+        }
+        if (bs)
+            for (int i = 0; i < 6; ++i) bs[6 * p + i] = hs.b[i];
+        gicp_stats& st = stats[p];
+        st.iters = hs.iters;
+        st.n_inliers = (int32_t)hs.n_inl;
+        st.cost = hs.cost;
+        st.converged = hs.converged;
+        st.status = nonfinite ? GICP_E_NONFINITE : qerr ? GICP_E_HIP : hs.status;
+        st.hip_error = 0;
+    }
+}
+
+void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm,
+                   float* const* covs_out, double* poses, double* Hs, double* bs, gicp_stats* stats, hipStream_t s) {
+    Sources src;
+    prepare_sources(c, nprob, probs, prm, covs_out, src, s);
+    const int64_t chunks = prepare_states(c, nprob, probs, prm, src, false);
     check(hipMemcpyAsync(c->d_state, c->h_state, nprob * sizeof(RegState), hipMemcpyHostToDevice, s));
     // 3. Gauss-Newton
     const bool queue = (prm->flags & GICP_FLAG_QUEUE) && !(prm->flags & GICP_FLAG_MULTI_LAUNCH);
@@ -958,29 +1065,7 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
         check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
         check(hipStreamSynchronize(s));
     }
-    for (int p = 0; p < nprob; ++p) {
-        const RegState& hs = c->h_state[p];
-        if (poses)
-            for (int i = 0; i < 16; ++i) poses[16 * p + i] = hs.pose[i];
-        if (Hs) {
-            int q = 0;
-            for (int i = 0; i < 6; ++i)
-                for (int j = i; j < 6; ++j) {
-                    Hs[36 * p + 6 * i + j] = hs.H[q];
-                    Hs[36 * p + 6 * j + i] = hs.H[q];
-                    ++q;
-                }
-        }
-        if (bs)
-            for (int i = 0; i < 6; ++i) bs[6 * p + i] = hs.b[i];
-        gicp_stats& st = stats[p];
-        st.iters = hs.iters;
-        st.n_inliers = (int32_t)hs.n_inl;
-        st.cost = hs.cost;
-        st.converged = hs.converged;
-        st.status = nonfinite ? GICP_E_NONFINITE : qerr ? GICP_E_HIP : hs.status;
-        st.hip_error = 0;
-    }
+    write_results(c, nprob, nonfinite, qerr, poses, Hs, bs, stats);
 }
 
 int fail(gicp_stats* stats, int nprob, const HipError& e) {
@@ -1045,6 +1130,80 @@ int gicp_register_batch(gicp_ctx* c, int nprob, const gicp_problem* probs, const
     if (stats) std::memcpy(stats, st.data(), nprob * sizeof(gicp_stats));
     for (int p = 0; p < nprob; ++p)
         if (st[p].status == GICP_E_HIP || st[p].status == GICP_E_NONFINITE) return st[p].status;
+    return GICP_OK;
+}
+
+int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_map* map, const double init_pose[16],
+               int motion, const gicp_params* prm, double* poses, double* Hs, double* bs, gicp_stats* stats,
+               void* stream) {
+    if (stats) std::memset(stats, 0, (size_t)std::max(nframes, 0) * sizeof(gicp_stats));
+    if (!c || !frames || !map || !init_pose || nframes < 1 || nframes > kMaxProblems || !valid_params(prm))
+        return GICP_E_ARG;
+    if (motion != GICP_MOTION_PREVIOUS && motion != GICP_MOTION_CONSTANT_VELOCITY) return GICP_E_ARG;
+    if (prm->flags & (GICP_FLAG_MULTI_LAUNCH | GICP_FLAG_QUEUE)) return GICP_E_ARG;
+    std::vector<gicp_problem> probs(nframes);
+    for (int i = 0; i < nframes; ++i) {
+        const gicp_frame& F = frames[i];
+        if (!F.src || F.n < 1 || F.n >= (1ll << 31)) return GICP_E_ARG;
+        if ((F.n + kChunk - 1) / kChunk >= (1ll << kChunkBits)) return GICP_E_ARG;
+        if (!F.src_covs && (!valid_cov_k(prm->k) || F.n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
+        gicp_problem& P = probs[i];
+        P.src = F.src;
+        P.src_covs = F.src_covs;
+        P.n = F.n;
+        P.map = map;
+        for (int j = 0; j < 16; ++j) P.init_pose[j] = (i == 0) ? init_pose[j] : (j % 5 == 0 ? 1.0 : 0.0);
+    }
+    std::vector<gicp_stats> st(nframes);
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        Sources src;
+        prepare_sources(c, nframes, probs.data(), prm, nullptr, src, s);
+        const int64_t grid = prepare_states(c, nframes, probs.data(), prm, src, true);
+        check(hipMemcpyAsync(c->d_state, c->h_state, nframes * sizeof(RegState), hipMemcpyHostToDevice, s));
+        check(hipMemcpyAsync(c->d_probs, c->h_probs, nframes * sizeof(ProbDev), hipMemcpyHostToDevice, s));
+        int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, grid);
+        double* part = ensure<double>(c->partials, (size_t)grid * kNumAcc);
+        int32_t* counter = ensure<int32_t>(c->track_counter, 1);
+        check(launch_fill_i32(counter, 1, 0, s));
+        const int acc = prm->precision;
+        if (prm->max_it > 0 && (prm->flags & GICP_FLAG_GRAPH)) {
+            hipGraphExec_t ge = track_graph(c, nframes, grid, prm->max_it, acc, motion, counter, chunk_prob, part);
+            for (int i = 0; i < nframes; ++i) {
+                const int pm = prof_open(c, GICP_PROF_LINEARIZE, (double)probs[i].n, -2, s, i);
+                check(hipGraphLaunch(ge, s));
+                prof_close(c, pm, s);
+            }
+        } else {
+            for (int i = 0; i < nframes; ++i) {
+                check(launch_track_begin(c->d_probs, nframes, counter, chunk_prob, grid, motion, s));
+                for (int it = 0; it < prm->max_it; ++it) {
+                    const int pl = prof_open(c, GICP_PROF_LINEARIZE, (double)probs[i].n, it, s, i);
+                    check(launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, true, false, s));
+                    prof_close(c, pl, s);
+                    const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, it, s, i);
+                    check(launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, false, true, s));
+                    prof_close(c, ps, s);
+                }
+            }
+        }
+        check(hipMemcpyAsync(c->h_state, c->d_state, nframes * sizeof(RegState), hipMemcpyDeviceToHost, s));
+        check(hipMemcpyAsync(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+        check(hipStreamSynchronize(s));
+        if (c->prof) prof_collect(c, 1 << 30);
+        const bool nonfinite = (c->h_err[0] & kErrNonFinite) != 0;
+        if (nonfinite) {
+            check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
+            check(hipStreamSynchronize(s));
+        }
+        write_results(c, nframes, nonfinite, false, poses, Hs, bs, st.data());
+    } catch (const HipError& e) {
+        return fail(stats, nframes, e);
+    }
+    if (stats) std::memcpy(stats, st.data(), nframes * sizeof(gicp_stats));
+    for (int i = 0; i < nframes; ++i)
+        if (st[i].status == GICP_E_HIP || st[i].status == GICP_E_NONFINITE) return st[i].status;
     return GICP_OK;
 }
 

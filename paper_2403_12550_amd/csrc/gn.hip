@@ -799,6 +799,70 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev*
 }
 
 // ---------------------------------------------------------------------------
+// Sequential tracking: the problems of a call run one after another, each
+// from a pose predicted on the device from the results of the previous ones.
+// Per problem: one k_track_begin (which problem is next comes from a device
+// counter, so that the same launches, or one captured graph, serve every
+// problem), then max_it pairs of k_gn_linearize_batch (grid = the largest
+// problem's chunk count; every problem uses partial slots from 0) and
+// k_gn_solve_track.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_track_begin(const ProbDev* __restrict__ probs, int nprob,
+                                                    int32_t* __restrict__ counter, int32_t* __restrict__ chunk_prob,
+                                                    int grid, int motion) {
+    __shared__ int s_i;
+    if (threadIdx.x == 0) s_i = *counter;
+    __syncthreads();
+    const int i = s_i;
+    const int nch = i < nprob ? probs[i].nchunks : 0;
+    for (int c = threadIdx.x; c < grid; c += blockDim.x) chunk_prob[c] = c < nch ? i : -1;
+    if (threadIdx.x != 0 || i >= nprob) return;
+    *counter = i + 1;
+    if (i == 0) return;   // the first problem starts from its given pose
+    // previous pose b; with constant velocity also the one before, a:
+    // T = b (a^-1 b), the last relative motion applied once more
+    const double* b = probs[i - 1].st->pose;
+    double T[16];
+    if (motion == GICP_MOTION_CONSTANT_VELOCITY && i >= 2) {
+        const double* a = probs[i - 2].st->pose;
+        double D[12];   // a^-1 b as [R | t] rows
+        for (int r = 0; r < 3; ++r) {
+            for (int col = 0; col < 3; ++col)
+                D[4 * r + col] = a[r] * b[col] + a[4 + r] * b[4 + col] + a[8 + r] * b[8 + col];
+            D[4 * r + 3] = a[r] * (b[3] - a[3]) + a[4 + r] * (b[7] - a[7]) + a[8 + r] * (b[11] - a[11]);
+        }
+        for (int r = 0; r < 3; ++r) {
+            for (int col = 0; col < 3; ++col)
+                T[4 * r + col] = b[4 * r] * D[col] + b[4 * r + 1] * D[4 + col] + b[4 * r + 2] * D[8 + col];
+            T[4 * r + 3] = b[4 * r] * D[3] + b[4 * r + 1] * D[7] + b[4 * r + 2] * D[11] + b[4 * r + 3];
+        }
+    } else {
+        for (int j = 0; j < 12; ++j) T[j] = b[j];
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+    RegState* st = probs[i].st;
+    for (int j = 0; j < 16; ++j) st->pose[j] = T[j];
+    for (int r = 0; r < 3; ++r) {
+        for (int col = 0; col < 3; ++col) st->Rf[3 * r + col] = (float)T[4 * r + col];
+        st->tf[r] = (float)T[4 * r + 3];
+    }
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_gn_solve_track(const ProbDev* __restrict__ probs,
+                                                                  const double* __restrict__ partials,
+                                                                  int32_t* __restrict__ chunk_prob) {
+    const int p = chunk_prob[0];
+    if (p < 0) return;
+    const ProbDev P = probs[p];
+    if (P.st->done) return;
+    solve_state(partials, P.nchunks, P.st);
+    __syncthreads();
+    if (P.st->done)
+        for (int c = threadIdx.x; c < P.nchunks; c += blockDim.x) chunk_prob[c] = -1;
+}
+
+// ---------------------------------------------------------------------------
 // Keyframe Gaussians (Sec. 3.1.2, Keyframe Selection; Sec. 3.2.1, Scale Aligning)
 // ---------------------------------------------------------------------------
 // keep[i] = 1 when R x_i + t has no map mean within r_max (the point adds a
@@ -967,6 +1031,35 @@ hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, int32_t* c
     }
     if (solve)
         hipLaunchKernelGGL(k_gn_solve_batch, dim3(nprob), dim3(kSolveThreads), 0, s, probs, (const double*)partials,
+                           chunk_prob);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter, int32_t* chunk_prob, int64_t grid,
+                              int motion, hipStream_t s) {
+    hipLaunchKernelGGL(k_track_begin, dim3(1), dim3(256), 0, s, probs, nprob, counter, chunk_prob, (int)grid, motion);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, int64_t grid, double* partials, int acc,
+                                     bool linearize, bool solve, hipStream_t s) {
+    if (linearize) {
+        switch (acc) {
+            case GICP_ACC_FP32:
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP32>, dim3((unsigned)grid), dim3(kLinThreads), 0, s,
+                                   probs, chunk_prob, partials);
+                break;
+            case GICP_ACC_FP64:
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP64>, dim3((unsigned)grid), dim3(kLinThreads), 0, s,
+                                   probs, chunk_prob, partials);
+                break;
+            default:
+                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_TWOSUM>, dim3((unsigned)grid), dim3(kLinThreads), 0,
+                                   s, probs, chunk_prob, partials);
+        }
+    }
+    if (solve)
+        hipLaunchKernelGGL(k_gn_solve_track, dim3(1), dim3(kSolveThreads), 0, s, probs, (const double*)partials,
                            chunk_prob);
     return hipGetLastError();
 }

@@ -162,6 +162,12 @@ hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_
 hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks, int acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
+// Sequential tracking (gicp_track): the next problem's chunk map and predicted
+// pose, then its iterations over a grid of the largest problem's chunks.
+hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter, int32_t* chunk_prob, int64_t grid,
+                              int motion, hipStream_t s);
+hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, int64_t grid, double* partials, int acc,
+                                     bool linearize, bool solve, hipStream_t s);
 
 // Incremental map update (grid.hip): merge the map's sorted run (okeys,
 // opts, ocov; m_old) with new points sorted on their own (nkeys, nvals into

@@ -63,7 +63,7 @@ def c1_problem(n: int = 5000, room_seed: int = 0, src_seed: int = 1, tgt_seed: i
 class C2Sequence:
     """Frame-to-map tracking workload.  Frames are rendered lazily and cached."""
 
-    def __init__(self, n_frames=100, scene_seed=10, traj_seed=11, map_seed=12,
+    def __init__(self, n_frames=100, scene_seed=10, traj_seed=14, map_seed=12,
                  map_size=1_000_000, voxel=0.02, K=C2_INTRINSICS, extent=(5.5, 5.0, 3.0), inward=False,
                  wall_band=None):
         self.K = K

@@ -280,3 +280,29 @@ def test_c4_no_reuse_bitwise(g, ctx, c4):
     for a, b in zip(*out):
         assert a.status == 0 and np.array_equal(a.pose, b.pose) and np.array_equal(a.H, b.H)
         assert np.array_equal(a.b, b.b) and a.iters == b.iters and a.n_inliers == b.n_inliers
+
+
+@pytest.mark.parametrize("motion", [0, 1])
+def test_c2_track_closed_loop_vs_oracle(g, ctx, c2, motion):
+    """The first 12 frames tracked in one gicp_track call (graph-replayed, the
+    timed form), each frame from the pose predicted from its own previous
+    estimates, against the oracle's tracking loop with the same motion model."""
+    from scipy.spatial import cKDTree
+
+    from oracle import tracking as ot
+    seq, frames, gm = c2
+    n = 12
+    src_cell = ctx.estimate_cell(frames[0], 20)
+    prm = g.params(k=20, eps=1e-3, r_max=R_MAX, max_it=MAX_IT, conv_rot=CONV, conv_trans=CONV,
+                   reg_mode=g.REG_PLANE, cell_src=src_cell, flags=g.FLAG_GRAPH)
+    _say("c2 track", motion)
+    res = ctx.track(frames[:n], gm, seq.poses[0], motion=motion, prm=prm)
+    assert all(r.status == 0 for r in res)
+    map_cov = oc.regularise6(seq.map_cov_raw, oc.REG_PLANE, 1e-3)
+    tree = cKDTree(seq.map_means.astype(np.float64))
+    est, _, ores = ot.track([seq.frame(i) for i in range(n)], seq.map_means, map_cov, seq.poses[0],
+                            motion=motion, r_max=R_MAX, max_it=MAX_IT, conv=CONV, tree=tree)
+    for i in range(n):
+        dr, dt = se3.pose_error(res[i].pose, est[i])
+        _say(f"  frame {i}: rot {dr:.2e} trans {dt:.2e} it {res[i].iters}/{ores[i].iters}")
+        assert dr < 1e-5 and dt < 1e-5

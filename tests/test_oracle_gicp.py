@@ -205,3 +205,46 @@ def test_c1_converges_near_truth():
     dr, dt = se3.pose_error(r.pose, p.T_gt)
     # resampled, noisy clouds: a sanity bound, not an exactness claim
     assert dr < 2e-3 and dt < 2e-3
+
+
+# ------------------------------------------------------------------ tracking loop
+def test_track_motion_models_on_exact_motion():
+    """On a sequence that moves by exactly the same relative motion every
+    frame, the constant-velocity prediction of frame i from the true poses of
+    frames i-2 and i-1 is the true pose of frame i (closed form), and the
+    previous-pose prediction is the pose of frame i-1."""
+    from oracle import se3
+    from oracle import tracking as ot
+    step = se3.exp_se3(np.array([0.01, -0.02, 0.015, 0.02, 0.0, -0.01]))
+    poses = [np.eye(4)]
+    for _ in range(5):
+        poses.append(poses[-1] @ step)
+    for i in range(2, 6):
+        cv = ot.predict(poses, i, np.eye(4), ot.CONSTANT_VELOCITY)
+        assert np.allclose(cv, poses[i], atol=1e-13)
+        assert np.array_equal(ot.predict(poses, i, np.eye(4), ot.PREVIOUS), poses[i - 1])
+    assert np.array_equal(ot.predict(poses, 1, np.eye(4), ot.CONSTANT_VELOCITY), poses[0])
+    T0 = se3.exp_se3(np.array([0.1, 0, 0, 1, 2, 3]))
+    assert np.array_equal(ot.predict([], 0, T0, ot.PREVIOUS), T0)
+    assert np.allclose(ot.rigid_inverse(T0) @ T0, np.eye(4), atol=1e-15)
+
+
+def test_track_exact_sequence_recovers_poses():
+    """Noise-free frames that are the map seen from known poses: tracking from
+    the first pose recovers every pose (both motion models)."""
+    import synth
+    from oracle import tracking as ot
+    room = synth.make_room(3)
+    mp, _ = synth.sample_surface(room, 6000, 5, 0.0)
+    mp = mp.astype(np.float32)
+    mc = oc.covariances(mp, 20)
+    rng = np.random.default_rng(4)
+    poses = [np.eye(4)]
+    for _ in range(4):
+        poses.append(poses[-1] @ synth.random_offset(rng, 1.0, 0.01))
+    frames = [((mp.astype(np.float64) - T[:3, 3]) @ T[:3, :3]).astype(np.float32) for T in poses]
+    for motion in (ot.PREVIOUS, ot.CONSTANT_VELOCITY):
+        est, _, res = ot.track(frames, mp, mc, poses[0], motion=motion, max_it=40, conv=1e-9)
+        for T, E in zip(poses, est):
+            dr, dt = se3.pose_error(E, T)
+            assert dr < 1e-6 and dt < 1e-6, (motion, dr, dt)
