@@ -1140,7 +1140,7 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
     if (!c || !frames || !map || !init_pose || nframes < 1 || nframes > kMaxProblems || !valid_params(prm))
         return GICP_E_ARG;
     if (motion != GICP_MOTION_PREVIOUS && motion != GICP_MOTION_CONSTANT_VELOCITY) return GICP_E_ARG;
-    if (prm->flags & (GICP_FLAG_MULTI_LAUNCH | GICP_FLAG_QUEUE)) return GICP_E_ARG;
+    if (prm->flags & GICP_FLAG_QUEUE) return GICP_E_ARG;
     std::vector<gicp_problem> probs(nframes);
     for (int i = 0; i < nframes; ++i) {
         const gicp_frame& F = frames[i];
@@ -1191,6 +1191,9 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
         check(hipMemcpyAsync(c->h_state, c->d_state, nframes * sizeof(RegState), hipMemcpyDeviceToHost, s));
         check(hipMemcpyAsync(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
         check(hipStreamSynchronize(s));
+        double units = 0.0;
+        for (int i = 0; i < nframes; ++i) units += (double)probs[i].n * c->h_state[i].iters;
+        c->queue_units = units;
         if (c->prof) prof_collect(c, 1 << 30);
         const bool nonfinite = (c->h_err[0] & kErrNonFinite) != 0;
         if (nonfinite) {

@@ -68,7 +68,8 @@ def test_track_vs_oracle(env, motion):
 def test_track_equals_register_from_same_inits(env, motion):
     """Every frame of the tracked sequence against gicp_register started from
     the pose the host predicts from the tracked estimates (the first frame
-    bitwise); the graph-replayed form bitwise equal to the launched form."""
+    bitwise); the persistent (default), launched and graph-replayed forms
+    bitwise equal."""
     g, ctx = env
     mp, mc, frames, poses = _sequence(seed=5)
     gm = ctx.map_build(g.to_soa(mp), g.to_soa(mc), cell=0.1)
@@ -76,12 +77,15 @@ def test_track_equals_register_from_same_inits(env, motion):
     cell = ctx.estimate_cell(F[0], 20)
     prm = g.params(cell_src=cell, **PRM)
     res = ctx.track(F, gm, poses[0], motion=motion, prm=prm)
+    res_l = ctx.track(F, gm, poses[0], motion=motion,
+                      prm=g.params(cell_src=cell, flags=g.FLAG_MULTI_LAUNCH, **PRM))
     res_g = ctx.track(F, gm, poses[0], motion=motion, prm=g.params(cell_src=cell, flags=g.FLAG_GRAPH, **PRM))
     est = [r.pose for r in res]
     for i in range(len(F)):
         _say("track vs register", motion, i)
-        assert np.array_equal(res_g[i].pose, res[i].pose) and np.array_equal(res_g[i].H, res[i].H)
-        assert res_g[i].iters == res[i].iters
+        for other in (res_l, res_g):
+            assert np.array_equal(other[i].pose, res[i].pose) and np.array_equal(other[i].H, res[i].H)
+            assert other[i].iters == res[i].iters and other[i].status == res[i].status
         r = ctx.register(F[i], gm, ot.predict(est, i, poses[0], motion), prm)
         if i == 0:
             assert np.array_equal(r.pose, res[0].pose) and np.array_equal(r.H, res[0].H)
@@ -108,4 +112,25 @@ def test_track_failure_and_args(env):
         ctx.track(F, gm, poses[0], motion=7, prm=g.params(**PRM))
     with pytest.raises(g.GicpError):
         ctx.track(F, gm, poses[0], prm=g.params(flags=g.FLAG_QUEUE, **PRM))
+    for flags in (g.FLAG_MULTI_LAUNCH, g.FLAG_GRAPH):
+        other = ctx.track(F, gm, poses[0], motion=0, prm=g.params(flags=flags, **PRM))
+        assert all(np.array_equal(a.pose, b.pose) and a.status == b.status for a, b in zip(res, other))
+    gm.close()
+
+
+def test_track_max_it_zero_and_single_frame(env):
+    """max_it = 0: every frame keeps its predicted pose (the first its given
+    pose); a one-frame sequence equals gicp_register."""
+    g, ctx = env
+    mp, mc, frames, poses = _sequence(n_frames=4, seed=9)
+    gm = ctx.map_build(g.to_soa(mp), g.to_soa(mc), cell=0.1)
+    F = [g.to_soa(f) for f in frames]
+    res = ctx.track(F, gm, poses[1], motion=1, prm=g.params(**dict(PRM, max_it=0)))
+    assert all(r.iters == 0 and r.status == 0 for r in res)
+    # (constant velocity from two equal poses is the identity motion, up to FP64 rounding)
+    assert np.array_equal(res[0].pose, poses[1]) and np.array_equal(res[1].pose, poses[1])
+    assert all(np.allclose(r.pose, poses[1], atol=1e-12) for r in res)
+    one = ctx.track(F[:1], gm, poses[0], motion=0, prm=g.params(**PRM))
+    reg = ctx.register(F[0], gm, poses[0], g.params(**PRM))
+    assert np.array_equal(one[0].pose, reg.pose) and np.array_equal(one[0].H, reg.H)
     gm.close()
