@@ -301,11 +301,16 @@ enum { GICP_MOTION_PREVIOUS = 0, GICP_MOTION_CONSTANT_VELOCITY = 1 };
  * sequence runs without a host round trip between frames.  Frame 0 starts
  * from init_pose.  Covariances of frames without src_covs are computed first,
  * in batched launches (they do not depend on any pose).  Per frame the same
- * Gauss-Newton iterations as gicp_register (a linearisation and a solve
- * launch per iteration; GICP_FLAG_GRAPH: each frame's launches replayed from
- * one captured graph, with equal results; GICP_FLAG_MULTI_LAUNCH is the
- * default form here; GICP_FLAG_NO_REUSE as for gicp_register;
- * GICP_FLAG_QUEUE is refused).  Outputs (host): poses [nframes][16], Hs [nframes][36],
+ * Gauss-Newton iterations as gicp_register, in one of three forms with equal
+ * results.  Default: iteration slots -- (linearise, solve) launch pairs whose
+ * frame the device picks; a frame's last solve predicts the next frame's pose
+ * and moves the device on to it, so each frame costs exactly its own
+ * iterations and the host launches pairs until the device reports (through
+ * host-mapped memory) that every frame has finished, at most 16 pairs ahead
+ * of it.  GICP_FLAG_MULTI_LAUNCH: max_it launch pairs per frame (pairs after
+ * convergence return at once).  GICP_FLAG_GRAPH: those launches replayed
+ * from one captured graph per frame.  GICP_FLAG_NO_REUSE as for
+ * gicp_register; GICP_FLAG_QUEUE is refused.  Outputs (host): poses [nframes][16], Hs [nframes][36],
  * bs [nframes][6] (each nullable), stats [nframes] (nullable).  A frame whose
  * registration fails (NO_CORR, DEGENERATE) keeps its last valid iterate, and
  * the next frames predict from it.  Synchronises the stream once.

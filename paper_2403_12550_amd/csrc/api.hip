@@ -1,10 +1,12 @@
 // Host runtime and C ABI of libgicp.so: context and growable workspace, grid
 // builds, map handles and the Gauss-Newton driver.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "common.hpp"
@@ -89,6 +91,9 @@ struct gicp_ctx {
     int state_cap = 0;
     QueueDev* d_queue = nullptr;
     Buf items, arrive, chunk_prob, track_counter;
+    int32_t* h_progress = nullptr;   // host-mapped progress of the tracking slots: problems done, slots run
+    int32_t* d_progress = nullptr;   // its device address
+    double slot_work = 0.0;          // slots of the last tracking call that did work
     int queue_workers[3] = {0, 0, 0};
     float* h_kth = nullptr;
     int h_kth_cap = 0;   // clouds the pinned estimate buffer holds
@@ -176,6 +181,18 @@ void prof_close(gicp_ctx* c, int mark, hipStream_t s) {
 // `iters_done` were launched but returned at once (converged) and are skipped.
 void prof_collect(gicp_ctx* c, int iters_done) {
     for (const ProfMark& m : c->marks) {
+        if (m.frame == -5) {
+            // a tracking slot (iter = slot index): the first slot_work slots did
+            // work, the rest found every problem finished
+            if (m.iter >= c->slot_work) continue;
+            float ms = 0.f;
+            check(hipEventSynchronize(m.b));
+            check(hipEventElapsedTime(&ms, m.a, m.b));
+            c->launches[m.group] += 1;
+            c->ms[m.group] += ms;
+            c->units[m.group] += m.group == GICP_PROF_LINEARIZE ? c->queue_units / c->slot_work : 1.0;
+            continue;
+        }
         if (m.frame >= 0) {
             // a tracked frame: its launches after convergence did no work; a
             // graph replay (iter -2) covers all of the frame's iterations
@@ -506,6 +523,7 @@ int gicp_destroy(gicp_ctx* c) {
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->h_pairs) (void)hipHostFree(c->h_pairs);
     if (c->h_jobs) (void)hipHostFree(c->h_jobs);
+    if (c->h_progress) (void)hipHostFree(c->h_progress);
     if (c->pairs_ev) (void)hipEventDestroy(c->pairs_ev);
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->d_state) (void)hipFree(c->d_state);
@@ -1165,10 +1183,51 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
         check(hipMemcpyAsync(c->d_probs, c->h_probs, nframes * sizeof(ProbDev), hipMemcpyHostToDevice, s));
         int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, grid);
         double* part = ensure<double>(c->partials, (size_t)grid * kNumAcc);
-        int32_t* counter = ensure<int32_t>(c->track_counter, 1);
-        check(launch_fill_i32(counter, 1, 0, s));
+        int32_t* counter = ensure<int32_t>(c->track_counter, 2);
+        check(launch_fill_i32(counter, 2, 0, s));
+        bool stalled = false;
         const int acc = prm->precision;
-        if (prm->max_it > 0 && (prm->flags & GICP_FLAG_GRAPH)) {
+        if (prm->max_it > 0 && !(prm->flags & (GICP_FLAG_GRAPH | GICP_FLAG_MULTI_LAUNCH))) {
+            // iteration slots: (linearise, solve) pairs whose problem the device
+            // chooses; the host launches until every problem has finished,
+            // at most kLead slots ahead of the device
+            if (!c->h_progress) {
+                check(hipHostMalloc(&c->h_progress, 2 * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
+                check(hipHostGetDevicePointer((void**)&c->d_progress, c->h_progress, 0));
+            }
+            volatile int32_t* hp = c->h_progress;
+            hp[0] = 0;
+            hp[1] = 0;
+            constexpr int64_t kLead = 16;
+            const int64_t max_slots = (int64_t)nframes * prm->max_it;
+            int64_t launched = 0;
+            stalled = false;
+            while (launched < max_slots && hp[0] < nframes) {
+                if (launched - hp[1] >= kLead) {
+                    // the device is behind: wait for it (bounded; a failed
+                    // stream is reported by the synchronisation below)
+                    const auto t0 = std::chrono::steady_clock::now();
+                    while (launched - hp[1] >= kLead && hp[0] < nframes) {
+                        std::this_thread::yield();
+                        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(20)) break;
+                    }
+                    if (launched - hp[1] >= kLead && hp[0] < nframes) {
+                        stalled = true;
+                        break;
+                    }
+                    continue;
+                }
+                const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, (int)launched, s, -5);
+                check(launch_track_slot(c->d_probs, nframes, counter, grid, part, acc, motion, c->d_progress, s, true,
+                                        false));
+                prof_close(c, pl, s);
+                const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, (int)launched, s, -5);
+                check(launch_track_slot(c->d_probs, nframes, counter, grid, part, acc, motion, c->d_progress, s, false,
+                                        true));
+                prof_close(c, ps, s);
+                ++launched;
+            }
+        } else if (prm->max_it > 0 && (prm->flags & GICP_FLAG_GRAPH)) {
             hipGraphExec_t ge = track_graph(c, nframes, grid, prm->max_it, acc, motion, counter, chunk_prob, part);
             for (int i = 0; i < nframes; ++i) {
                 const int pm = prof_open(c, GICP_PROF_LINEARIZE, (double)probs[i].n, -2, s, i);
@@ -1191,15 +1250,20 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
         check(hipMemcpyAsync(c->h_state, c->d_state, nframes * sizeof(RegState), hipMemcpyDeviceToHost, s));
         check(hipMemcpyAsync(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
         check(hipStreamSynchronize(s));
-        double units = 0.0;
-        for (int i = 0; i < nframes; ++i) units += (double)probs[i].n * c->h_state[i].iters;
+        double units = 0.0, work = 0.0;
+        for (int i = 0; i < nframes; ++i) {
+            units += (double)probs[i].n * c->h_state[i].iters;
+            work += c->h_state[i].iters;
+        }
         c->queue_units = units;
+        c->slot_work = work;
         if (c->prof) prof_collect(c, 1 << 30);
         const bool nonfinite = (c->h_err[0] & kErrNonFinite) != 0;
         if (nonfinite) {
             check(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
             check(hipStreamSynchronize(s));
         }
+        if (stalled) throw HipError{hipErrorLaunchTimeOut};
         write_results(c, nframes, nonfinite, false, poses, Hs, bs, st.data());
     } catch (const HipError& e) {
         return fail(stats, nframes, e);

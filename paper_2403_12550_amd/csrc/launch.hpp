@@ -166,6 +166,11 @@ hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hi
 // pose, then its iterations over a grid of the largest problem's chunks.
 hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter, int32_t* chunk_prob, int64_t grid,
                               int motion, hipStream_t s);
+// One iteration slot of sequential tracking.  ctl: device int32[2] (the
+// current problem, slots run; zero before the first slot); progress:
+// host-mapped int32[2] receiving (problems finished, slots run).
+hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int64_t grid, double* partials, int acc,
+                             int motion, int32_t* progress, hipStream_t s, bool linearize, bool solve);
 hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, int64_t grid, double* partials, int acc,
                                      bool linearize, bool solve, hipStream_t s);
 
