@@ -45,11 +45,11 @@ GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix 
 # linearisation per point and iteration over the launches that did work.
 # Valid for the kernels as they were when the counters were taken (None: not
 # taken for the current kernels).
-TRAFFIC_BYTES_PER_UNIT = {0: None}
+TRAFFIC_BYTES_PER_UNIT = {0: 305.1}
 # Wavefront VALU instructions per unit from rocprofv3 SQ_INSTS_VALU on the same
-# runs, and the chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64
+# runs (profiles/hbm_traffic__c2_track_pmc.md), and the chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64
 # instruction per SIMD every 4 cycles (16 lanes a cycle) at 2.4 GHz.
-VALU_INSTS_PER_UNIT = {0: None}
+VALU_INSTS_PER_UNIT = {0: 127.3}
 VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
 MOTION_NAMES = {0: "previous", 1: "constant_velocity"}
 
@@ -190,6 +190,9 @@ def main():
     ap.add_argument("--regularisation-study", type=int, default=0, metavar="FRAMES",
                     help="closed-loop tracking of the first FRAMES frames with no / plane / ellipse "
                          "regularisation of map and frame covariances; reports the trajectory error of each")
+    ap.add_argument("--tracking-only", action="store_true",
+                    help="run only the warm-up and the timed tracking call, and print their work units (point "
+                         "iterations) with the timing; for counter profiles of the tracking kernels")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "the HBM byte counters) and exit")
@@ -252,13 +255,22 @@ def main():
     # --- headline: closed-loop tracking, one gicp_track call for the K frames
     # in its default form (iteration slots: each frame costs its own
     # iterations, the device moves on to the next frame itself)
-    ctx.track(frames[:max(1, args.warmup)], gmap, T0, motion, prm(0))
+    tw = ctx.track(frames[:max(1, args.warmup)], gmap, T0, motion, prm(0))
     elapsed, tr = timed(lambda: ctx.track(frames[:K], gmap, T0, motion, prm(0)))
     fps = K / elapsed
     statuses = sorted(set(int(r.status) for r in tr))
     iters = [r.iters for r in tr]
     log(f"tracking form ({K} frames, one call): {fps:.1f} frames/s, mean iterations {np.mean(iters):.2f}, "
         f"statuses {statuses}")
+    if args.tracking_only:
+        def units(res):
+            return int(sum(int(npts[i]) * r.iters for i, r in enumerate(res)))
+        print(json.dumps({"tracking_only": True, "frames": K, "value": round(fps, 3), "units_timed": units(tr),
+                          "units_warmup": units(tw), "slots_timed": int(sum(iters)),
+                          "slots_warmup": int(sum(r.iters for r in tw))}), flush=True)
+        gmap.close()
+        ctx.close()
+        return
     # the other two forms of the same call (max_it launch pairs per frame,
     # launched or replayed from a graph): equal poses
     el_launch, tr_l = timed(lambda: ctx.track(frames[:K], gmap, T0, motion, prm(g.FLAG_MULTI_LAUNCH)))
