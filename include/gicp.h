@@ -265,6 +265,30 @@ int gicp_register(gicp_ctx* ctx, const float* src, const float* src_covs, int64_
                   double pose[16], double H[36], double b[6], float* src_covs_out,
                   gicp_stats* stats, void* stream);
 
+/* gicp_register with the pose input and every output in device memory, for
+ * callers that chain registrations on the device or capture them in a HIP
+ * graph (Sec. 3, Eq. MLE_for_T: the same Gauss-Newton minimisation, the same
+ * kernels and bitwise the same results as gicp_register).  Nothing is copied
+ * to or from the host and the call does not synchronise the stream.
+ *   init_pose  device double[16] (row-major), read when the stream reaches it
+ *   pose, H, b device double[16], double[36] (full symmetric), double[6]
+ *   stats      nullable device gicp_stats; stats->status carries the
+ *              registration's status (GICP_E_NO_CORR, GICP_E_DEGENERATE, or
+ *              GICP_E_NONFINITE for a non-finite input, which also stays
+ *              recorded for the next gicp_sync_status)
+ *   src_covs, src_covs_out  as gicp_register (device)
+ * The return value reports only what the host can check (arguments, HIP
+ * launch errors).  GICP_FLAG_GRAPH is refused (the call is itself meant for
+ * capture); the default, GICP_FLAG_MULTI_LAUNCH and GICP_FLAG_QUEUE forms are
+ * accepted.  For capture: params->cell_src > 0 (an estimated cell size
+ * synchronises), and one call of at least the same sizes on the context
+ * before capturing (its workspaces grow on demand, and an allocation cannot
+ * be captured); a captured graph stays valid while no larger call on the
+ * same context grows those workspaces. */
+int gicp_register_dev(gicp_ctx* ctx, const float* src, const float* src_covs, int64_t n, const gicp_map* map,
+                      const double* init_pose, const gicp_params* params, double* pose, double* H, double* b,
+                      float* src_covs_out, gicp_stats* stats, void* stream);
+
 /* Registers `nprob` independent problems in one call (same method and
  * parameters as gicp_register; problems may differ in size and map).  Source
  * covariances of all problems come from one segmented grid and one set of

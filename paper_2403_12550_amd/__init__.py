@@ -246,6 +246,31 @@ class Context:
         return RegisterResult(np.array(pose[:]).reshape(4, 4), np.array(H[:]).reshape(6, 6), np.array(b[:]),
                               stats.iters, stats.n_inliers, stats.cost, bool(stats.converged), st)
 
+    def register_dev(self, src, gmap: Map, init_pose, pose, H, b, prm: Params | None = None, src_covs=None,
+                     src_covs_out=None, stats=None):
+        """gicp_register_dev: init_pose [16] float64, pose [16], H [36], b [6]
+        float64 and stats (a uint8 tensor of sizeof(gicp_stats) bytes, or
+        None) are CUDA tensors; nothing is synchronised or copied to the host."""
+        import torch
+        _check_f32_cuda(src, 3, "src")
+        for t, k, name in ((init_pose, 16, "init_pose"), (pose, 16, "pose"), (H, 36, "H"), (b, 6, "b")):
+            if t.dtype != torch.float64 or not t.is_cuda or t.numel() != k or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of {k} values")
+        if stats is not None and (not stats.is_cuda or stats.numel() * stats.element_size() < C.sizeof(Stats)):
+            raise ValueError("stats must be a CUDA tensor of at least sizeof(gicp_stats) bytes")
+        prm = prm or params()
+        st = lib().gicp_register_dev(self.handle, _ptr(src), _ptr(src_covs), src.shape[1], gmap.handle,
+                                     _ptr(init_pose), C.byref(prm), _ptr(pose), _ptr(H), _ptr(b),
+                                     _ptr(src_covs_out), _ptr(stats), _stream())
+        if st != GICP_OK:
+            raise GicpError(st, "gicp_register_dev")
+
+    @staticmethod
+    def stats_from_bytes(raw) -> dict:
+        """Decodes a gicp_stats read back from the device (numpy uint8)."""
+        a = np.frombuffer(np.asarray(raw, np.uint8).tobytes()[:_STATS_DT.itemsize], _STATS_DT)[0]
+        return {k: a[k].item() for k in _STATS_DT.names}
+
     def register_pair(self, src, map_means, map_covs, init_pose, prm: Params | None = None, src_covs=None,
                       map_cell: float = 0.0) -> RegisterResult:
         """The problem-statement form: registers src against Gaussians (means

@@ -104,6 +104,7 @@ SIGNATURES = {
     "gicp_map_nearest": (C.c_int, [P, P, P, I64, C.c_float, P, P, P, P, P]),
     "gicp_register": (C.c_int, [P, P, P, I64, P, D16, C.POINTER(Params), D16, D36, D6, P,
                                 C.POINTER(Stats), P]),
+    "gicp_register_dev": (C.c_int, [P, P, P, I64, P, P, C.POINTER(Params), P, P, P, P, P, P]),
     "gicp_track": (C.c_int, [P, C.c_int, C.POINTER(Frame), P, D16, C.c_int, C.POINTER(Params), P, P, P,
                              C.POINTER(Stats), P]),
     "gicp_register_pair": (C.c_int, [P, P, P, I64, P, P, I64, C.c_float, D16, C.POINTER(Params), D16, D36,

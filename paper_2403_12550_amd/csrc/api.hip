@@ -91,6 +91,8 @@ struct gicp_ctx {
     int state_cap = 0;
     QueueDev* d_queue = nullptr;
     Buf items, arrive, chunk_prob, track_counter;
+    RegState* dev_state = nullptr;   // gicp_register_dev: its own state and descriptor, allocated once
+    ProbDev* dev_probs = nullptr;    // (never reallocated, so graphs that capture the call stay valid)
     int32_t* h_progress = nullptr;   // host-mapped progress of the tracking slots: problems done, slots run
     int32_t* d_progress = nullptr;   // its device address
     double slot_work = 0.0;          // slots of the last tracking call that did work
@@ -493,6 +495,8 @@ int gicp_create(gicp_ctx** out, int device) {
         check(hipMalloc(&c->d_err, 256));
         check(hipMemset(c->d_err, 0, 256));
         check(hipMalloc(&c->d_queue, sizeof(QueueDev)));
+        check(hipMalloc(&c->dev_state, sizeof(RegState)));
+        check(hipMalloc(&c->dev_probs, sizeof(ProbDev)));
         check(hipHostMalloc(&c->h_err, 256));
         check(hipHostMalloc(&c->h_kth, kEstimateSamples * sizeof(float)));
         c->h_kth_cap = 1;
@@ -531,6 +535,8 @@ int gicp_destroy(gicp_ctx* c) {
     if (c->d_probs) (void)hipFree(c->d_probs);
     if (c->h_probs) (void)hipHostFree(c->h_probs);
     if (c->d_queue) (void)hipFree(c->d_queue);
+    if (c->dev_state) (void)hipFree(c->dev_state);
+    if (c->dev_probs) (void)hipFree(c->dev_probs);
     release(c->items);
     release(c->arrive);
     release(c->chunk_prob);
@@ -1126,6 +1132,71 @@ int gicp_register(gicp_ctx* c, const float* src, const float* src_covs, int64_t 
     }
     if (stats) *stats = st;
     return st.status;
+}
+
+int gicp_register_dev(gicp_ctx* c, const float* src, const float* src_covs, int64_t n, const gicp_map* map,
+                      const double* init_pose, const gicp_params* prm, double* pose, double* H, double* b,
+                      float* src_covs_out, gicp_stats* stats, void* stream) {
+    if (!c || !src || !map || !init_pose || !prm || !pose || !H || !b || n < 1 || n >= (1ll << 31))
+        return GICP_E_ARG;
+    if (!src_covs && (!valid_cov_k(prm->k) || n < prm->k || !valid_mode(prm->reg_mode))) return GICP_E_ARG;
+    if (!valid_params(prm) || (prm->flags & GICP_FLAG_GRAPH)) return GICP_E_ARG;
+    if ((n + kChunk - 1) / kChunk >= (1ll << kChunkBits)) return GICP_E_ARG;
+    try {
+        check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        gicp_problem P;
+        P.src = src;
+        P.src_covs = src_covs;
+        P.n = n;
+        P.map = map;
+        for (int i = 0; i < 16; ++i) P.init_pose[i] = (i % 5 == 0) ? 1.0 : 0.0;   // replaced on the device
+        float* outs[1] = {src_covs_out};
+        Sources srcs;
+        prepare_sources(c, 1, &P, prm, outs, srcs, s);
+        const int64_t chunks = prepare_states(c, 1, &P, prm, srcs, false);
+        ProbDev pd = c->h_probs[0];
+        pd.st = c->dev_state;
+        StateInit si;
+        si.conv_rot = prm->conv_rot;
+        si.conv_trans = prm->conv_trans;
+        si.max_it = prm->max_it;
+        si.acc = prm->precision;
+        check(launch_state_init(pd, c->dev_probs, si, init_pose, c->dev_state, s));
+        if (prm->max_it > 0) {
+            if (prm->flags & GICP_FLAG_MULTI_LAUNCH) {
+                const int nb = gn_blocks(n);
+                double* part = ensure<double>(c->partials, (size_t)nb * kNumAcc);
+                for (int it = 0; it < prm->max_it; ++it) {
+                    check(launch_gn_linearize(pd, part, nb, prm->precision, s));
+                    check(launch_gn_solve(part, nb, c->dev_state, s));
+                }
+            } else if (prm->flags & GICP_FLAG_QUEUE) {
+                const uint64_t cap64 = (uint64_t)chunks * (uint64_t)prm->max_it;
+                if (cap64 >= (1ull << 31)) throw HipError{hipErrorInvalidValue};
+                const uint32_t cap = (uint32_t)cap64;
+                uint32_t* items = ensure<uint32_t>(c->items, cap);
+                uint32_t* arrive = ensure<uint32_t>(c->arrive, 1);
+                double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
+                const int acc = prm->precision;
+                if (!c->queue_workers[acc]) c->queue_workers[acc] = gn_queue_workers(acc);
+                const int workers = (int)std::min<int64_t>(chunks, c->queue_workers[acc]);
+                check(launch_gn_queue(c->dev_probs, 1, c->d_queue, items, cap, (uint32_t)chunks, arrive, part, workers,
+                                      acc, s));
+            } else {
+                int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, chunks);
+                double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
+                check(launch_chunk_map(c->dev_probs, 1, chunk_prob, s));
+                for (int it = 0; it < prm->max_it; ++it)
+                    check(launch_gn_iteration_batch(c->dev_probs, 1, chunk_prob, chunks, part, prm->precision, true,
+                                                    true, s));
+            }
+        }
+        check(launch_state_out(c->dev_state, c->d_err, pose, H, b, stats, s));
+        return GICP_OK;
+    } catch (const HipError& e) {
+        return status_of(e);
+    }
 }
 
 int gicp_register_batch(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp_params* prm, double* poses,

@@ -947,6 +947,59 @@ __global__ __launch_bounds__(kSolveThreads) void k_slot_solve(const ProbDev* __r
 }
 
 // ---------------------------------------------------------------------------
+// Device-resident registration (gicp_register_dev): the problem descriptor and
+// the initial state are written by a kernel from its arguments and the
+// device initial pose, and the results are written by a kernel to device
+// outputs, so that the whole call is stream-ordered device work that a HIP
+// graph can capture.
+// ---------------------------------------------------------------------------
+__global__ void k_state_init(ProbDev pd, ProbDev* __restrict__ dst, StateInit si, const double* __restrict__ init,
+                             RegState* __restrict__ st) {
+    if (threadIdx.x != 0) return;
+    *dst = pd;
+    for (int j = 0; j < 16; ++j) st->pose[j] = init[j];
+    for (int j = 0; j < 21; ++j) st->H[j] = 0.0;
+    for (int j = 0; j < 6; ++j) st->b[j] = 0.0;
+    st->cost = 0.0;
+    st->n_inl = 0.0;
+    st->conv_rot = si.conv_rot;
+    st->conv_trans = si.conv_trans;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) st->Rf[3 * r + c] = (float)init[4 * r + c];
+        st->tf[r] = (float)init[4 * r + 3];
+    }
+    st->iters = 0;
+    st->max_it = si.max_it;
+    st->done = si.max_it <= 0 ? 1 : 0;
+    st->status = GICP_OK;
+    st->converged = 0;
+    st->acc = si.acc;
+}
+
+__global__ void k_state_out(const RegState* __restrict__ st, const int* __restrict__ err, double* __restrict__ pose,
+                            double* __restrict__ H, double* __restrict__ b, gicp_stats* __restrict__ stats) {
+    const int t = threadIdx.x;
+    if (t < 16) pose[t] = st->pose[t];
+    if (t < 36) {
+        const int i = t / 6, j = t % 6;
+        const int lo = i < j ? i : j, hi = i < j ? j : i;
+        H[t] = st->H[lo * 6 - lo * (lo - 1) / 2 + (hi - lo)];
+    }
+    if (t < 6) b[t] = st->b[t];
+    if (t == 0 && stats) {
+        gicp_stats o;
+        o.iters = st->iters;
+        o.n_inliers = (int32_t)st->n_inl;
+        o.cost = st->cost;
+        o.converged = st->converged;
+        o.status = (*err & kErrNonFinite) ? GICP_E_NONFINITE : st->status;
+        o.hip_error = 0;
+        o.reserved = 0;
+        *stats = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Keyframe Gaussians (Sec. 3.1.2, Keyframe Selection; Sec. 3.2.1, Scale Aligning)
 // ---------------------------------------------------------------------------
 // keep[i] = 1 when R x_i + t has no map mean within r_max (the point adds a
@@ -1170,6 +1223,18 @@ hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int6
     if (solve)
         hipLaunchKernelGGL(k_slot_solve, dim3(1), dim3(kSolveThreads), 0, s, probs, nprob, (const double*)partials, ctl,
                            motion, progress);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_init(const ProbDev& pd, ProbDev* dst, const StateInit& si, const double* init, RegState* st,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, pd, dst, si, init, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_out(const RegState* st, const int* err, double* pose, double* H, double* b,
+                            gicp_stats* stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_out, dim3(1), dim3(64), 0, s, st, err, pose, H, b, stats);
     return hipGetLastError();
 }
 

@@ -115,6 +115,12 @@ struct __align__(256) RegState {
     int32_t acc;
 };
 
+// The scalar settings of a registration state (gicp_register_dev).
+struct StateInit {
+    double conv_rot, conv_trans;
+    int32_t max_it, acc;
+};
+
 struct MapView {
     GridView g;
     const float4* scov;   // [m][2]: {xx, xy, xz, yy}, {yz, zz, 0, 0}
@@ -162,6 +168,13 @@ hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_
 hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks, int acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
+// Device-resident registration: descriptor and state from kernel arguments
+// and the device initial pose; results (H full symmetric [36]) to device
+// outputs, the status NONFINITE when the context's error word holds it.
+hipError_t launch_state_init(const ProbDev& pd, ProbDev* dst, const StateInit& si, const double* init, RegState* st,
+                             hipStream_t s);
+hipError_t launch_state_out(const RegState* st, const int* err, double* pose, double* H, double* b,
+                            gicp_stats* stats, hipStream_t s);
 // Sequential tracking (gicp_track): the next problem's chunk map and predicted
 // pose, then its iterations over a grid of the largest problem's chunks.
 hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter, int32_t* chunk_prob, int64_t grid,
