@@ -1,7 +1,14 @@
 """The learned warm start end to end on a small scale: a dataset of
-G-ICP-labelled pairs from seeded trajectories, training through the library's
-kernels, and the comparison with the constant-velocity initial pose on
-held-out trajectories (with the fallback)."""
+G-ICP-labelled pairs (nearest-point rows) from seeded trajectories, training
+through the library's kernels, and the comparison on held-out trajectories
+with the identity start (an independent pair with no prior) and the
+constant-velocity start.  What it measures is recorded, not assumed: on these
+sparse resampled frames the network's initial pose is not better than either
+(the figures at 50k training pairs are in the design notes); the test asserts
+that the pipeline is sound -- training reduces the loss, registrations from
+the network's poses reach the labels as the other starts do, and with the
+constant-velocity fallback nothing converges less often than the plain
+method."""
 import numpy as np
 import pytest
 
@@ -16,20 +23,28 @@ def test_warmstart_train_and_evaluate():
     from paper_2403_12550_amd import warmstart_train as wt
     torch.cuda.set_device(0)
     print("[case] warmstart small", flush=True)
+    train_seeds = list(range(wt.TRAIN_SEED0, wt.TRAIN_SEED0 + 12))
+    test_seeds = list(range(wt.TEST_SEED0, wt.TEST_SEED0 + 2))
+    # serial generation: this process may already have initialised the GPU runtime
+    train, test = wt.generate(train_seeds, 1), wt.generate(test_seeds, 1)
     ctx = g.Context(0)
     net = ws.WarmStartNet(ctx, 0)
-    X, Y = wt.build_dataset(g, ctx, net, list(range(wt.TRAIN_SEED0, wt.TRAIN_SEED0 + 6)), workers=4)
-    assert X.shape == (600, 4096, 6) and Y.shape == (600, 6)
+    X, Y = wt.build_dataset(g, ctx, net, train_seeds, train)
+    assert X.shape == (1200, 4096, 6) and Y.shape == (1200, 6)
     # labels are relative poses of at most 8 cm / 4 degrees per frame
     assert float(Y[:, :3].norm(dim=1).max()) < np.radians(4.5)
     y0, cache, _ = net.forward(X[:64], want_cache=True)
     first = float(net.backward(X[:64], cache, y0, Y[:64])[1].item())
-    hist = wt.train(net, X, Y, epochs=6, batch=32, lr=1e-3)
+    hist = wt.train(net, X, Y, epochs=12, batch=32, lr=1e-3)
     assert hist[-1] < 0.5 * first, (first, hist)
-    ev = wt.evaluate(g, ctx, net, [wt.TEST_SEED0], workers=1)
-    assert ev["pairs"] == 100
-    # the fallback converges at least wherever the constant-velocity start does
-    assert ev["net_fallback"]["converged_frac"] >= ev["cv"]["converged_frac"] - 1e-9
-    for name in ("cv", "net", "net_fallback"):
-        assert np.isfinite(ev[name]["mean_iterations"])
+    ev = wt.evaluate(g, ctx, net, test_seeds, test)
+    print("[case] eval", {k: (v if not isinstance(v, dict) else {kk: round(vv, 5) for kk, vv in v.items()})
+                          for k, v in ev.items()}, flush=True)
+    assert ev["pairs"] == 200
+    net_, idn, cv = ev["net"], ev["identity"], ev["cv"]
+    for r in (net_, idn, cv, ev["net_fallback"]):
+        assert r["max_trans_err_m"] < 1e-4   # every start reaches the label
+    assert np.isfinite(net_["init_mean_trans_err_m"]) and net_["init_mean_trans_err_m"] < 0.5
+    # with the constant-velocity fallback nothing converges less often than the plain method
+    assert ev["net_fallback"]["converged_frac"] >= cv["converged_frac"] - 1e-9
     ctx.close()
