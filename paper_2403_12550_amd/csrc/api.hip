@@ -90,7 +90,7 @@ struct gicp_ctx {
     ProbDev* h_probs = nullptr;      // pinned [state_cap]
     int state_cap = 0;
     QueueDev* d_queue = nullptr;
-    Buf items, arrive, chunk_prob, track_counter;
+    Buf items, arrive, chunk_prob, track_counter, slot_sync;
     RegState* dev_state = nullptr;   // gicp_register_dev: its own state and descriptor, allocated once
     ProbDev* dev_probs = nullptr;    // (never reallocated, so graphs that capture the call stay valid)
     int32_t* h_progress = nullptr;   // host-mapped progress of the tracking slots: problems done, slots run
@@ -521,7 +521,7 @@ int gicp_destroy(gicp_ctx* c) {
                    &c->grid.spts, &c->grid.table, &c->covs, &c->partials, &c->kth, &c->ssrc, &c->sscov,
                    &c->nn_prev, &c->nn_cache, &c->overflow, &c->mlp_pairs, &c->mlp_pmax, &c->mlp_parg, &c->mlp_gpair,
                    &c->mlp_lpair, &c->dep_pts, &c->dep_vox, &c->dep_flags, &c->dep_pos, &c->dep_scan, &c->dep_misc,
-                   &c->ins_cov, &c->kth_jobs, &c->track_counter})
+                   &c->ins_cov, &c->kth_jobs, &c->track_counter, &c->slot_sync})
         release(*b);
     for (auto& ge : c->graphs) (void)hipGraphExecDestroy(ge.exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -1254,8 +1254,8 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
         check(hipMemcpyAsync(c->d_probs, c->h_probs, nframes * sizeof(ProbDev), hipMemcpyHostToDevice, s));
         int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, grid);
         double* part = ensure<double>(c->partials, (size_t)grid * kNumAcc);
-        int32_t* counter = ensure<int32_t>(c->track_counter, 2);
-        check(launch_fill_i32(counter, 2, 0, s));
+        int32_t* counter = ensure<int32_t>(c->track_counter, 3);
+        check(launch_fill_i32(counter, 3, 0, s));
         bool stalled = false;
         const int acc = prm->precision;
         if (prm->max_it > 0 && !(prm->flags & (GICP_FLAG_GRAPH | GICP_FLAG_MULTI_LAUNCH))) {
@@ -1266,6 +1266,10 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
                 check(hipHostMalloc(&c->h_progress, 2 * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
                 check(hipHostGetDevicePointer((void**)&c->d_progress, c->h_progress, 0));
             }
+            // the slots' hand-over words, zero (int32 words) before the first slot
+            const int64_t sync_words = (int64_t)(slot_sync_bytes() / sizeof(int32_t));
+            int32_t* sync = ensure<int32_t>(c->slot_sync, (size_t)sync_words);
+            check(launch_fill_i32(sync, sync_words, 0, s));
             volatile int32_t* hp = c->h_progress;
             hp[0] = 0;
             hp[1] = 0;
@@ -1289,13 +1293,9 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
                     continue;
                 }
                 const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, (int)launched, s, -5);
-                check(launch_track_slot(c->d_probs, nframes, counter, grid, part, acc, motion, c->d_progress, s, true,
-                                        false));
+                check(launch_track_slot(c->d_probs, nframes, counter, (int)(launched & 1), grid, part, acc, motion,
+                                        c->d_progress, sync, s));
                 prof_close(c, pl, s);
-                const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, (int)launched, s, -5);
-                check(launch_track_slot(c->d_probs, nframes, counter, grid, part, acc, motion, c->d_progress, s, false,
-                                        true));
-                prof_close(c, ps, s);
                 ++launched;
             }
         } else if (prm->max_it > 0 && (prm->flags & GICP_FLAG_GRAPH)) {

@@ -414,11 +414,38 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     return true;
 }
 
+// Hand-over of values between workgroups of one launch without cache
+// write-back.  An agent-scope fence writes back the whole L2 of the XCD
+// (measured: a launch of 1,057 workgroups that each fence before a counter
+// update takes 110 us against 44 us without), so the values handed over are
+// written and read with agent-scope (device-coherent) atomic accesses, and the
+// hand-over only orders them: the writer waits for its stores to complete
+// before the counter update, and the reader's loads are not moved above the
+// counter update.
+__device__ __forceinline__ void store_dev(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_dev(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt with vmcnt = 0 and the other counters left alone (gfx9 encoding)
+constexpr int kWaitVm0 = (0x7 << 4) | (0xf << 8);
+__device__ __forceinline__ void handover_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+}
+__device__ __forceinline__ void handover_acquire() {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, G
 // lanes per point.  The group's first lane stores the point's 29 values in an
 // LDS row (zeros when it is not an inlier); threads 0..28 then sum one column
-// each over the 64 rows in a fixed order, and write the chunk's FP64 partial.
-template <int ACC, int G = kGroup>
+// each over the 64 rows in a fixed order, and write the chunk's FP64 partial
+// (with DEV device-coherently, completed before the closing barrier, for a
+// hand-over within the launch).
+template <int ACC, int G = kGroup, bool DEV = false>
 __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, const float* R, const float* t,
                                                 double* __restrict__ out) {
     __shared__ float s_val[kChunk][kNumAcc + 1];
@@ -436,7 +463,14 @@ __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, con
     if (threadIdx.x < kNumAcc * kSumParts) {
         const int col = threadIdx.x / kSumParts, part = threadIdx.x % kSumParts;
         const double r = column_sum_split<ACC>(&s_val[0][col], kNumAcc + 1, part);
-        if (part == 0) out[col] = r;
+        if (part == 0) {
+            if (DEV) {
+                store_dev(&out[col], r);
+                handover_release();
+            } else {
+                out[col] = r;
+            }
+        }
     }
     __syncthreads();
 }
@@ -498,15 +532,34 @@ __device__ __forceinline__ void exp_se3(const double xi[6], double T[16]) {
 
 }  // namespace
 
-// Thread-0 part of the solve: v holds the 29 reduced sums; H and L live in
-// LDS (workspace of 72 doubles) so that the single-thread FP64 solve does not
-// raise the register footprint of the kernels that embed it.
-__device__ __noinline__ void solve_update(const double* v, RegState* st, double* H, double* L) {
-    // the state's scalar fields read below, loaded together before any store
-    // (the state was last written on another compute unit: one round trip)
-    const int32_t iters = st->iters + 1;
-    const int32_t max_it = st->max_it;
-    const double conv_rot = st->conv_rot, conv_trans = st->conv_trans;
+// The state fields the update reads, fetched by the reducing threads while
+// their partials are in flight (the state was last written on another
+// compute unit: fetched inside the update they would cost two more round
+// trips on its single thread), one 8-byte word per thread: pose[16],
+// conv_rot, conv_trans, and the word holding iters and max_it.
+constexpr int kPreFields = 19;
+static_assert(offsetof(RegState, conv_rot) % 8 == 0 && offsetof(RegState, conv_trans) % 8 == 0 &&
+                  offsetof(RegState, iters) % 8 == 0 && offsetof(RegState, max_it) == offsetof(RegState, iters) + 4,
+              "prefetched state words");
+
+__device__ __forceinline__ int pre_word(int t) {
+    return t < 16 ? t
+                  : (t == 16 ? (int)(offsetof(RegState, conv_rot) / 8)
+                             : (t == 17 ? (int)(offsetof(RegState, conv_trans) / 8) : (int)(offsetof(RegState, iters) / 8)));
+}
+
+// Thread-0 part of the solve: v holds the 29 reduced sums, pre the words
+// above; H and L live in LDS (workspace of 72 doubles).  Inlined where the
+// kernel bounds its registers (the iteration slots); called through
+// solve_update elsewhere, so that the single-thread FP64 code does not raise
+// the register footprint of the kernels that embed it.
+__device__ __forceinline__ void solve_update_inl(const double* v, const double* pre, RegState* st, double* H,
+                                                 double* L) {
+    int32_t im[2];
+    __builtin_memcpy(im, &pre[18], 8);
+    const int32_t iters = im[0] + 1;
+    const int32_t max_it = im[1];
+    const double conv_rot = pre[16], conv_trans = pre[17];
     int q = 0;
     for (int i = 0; i < 6; ++i)
         for (int j = i; j < 6; ++j) {
@@ -573,9 +626,9 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
 #pragma unroll
     for (int i = 0; i < 6; ++i) xi[i] = -xi[i];
     // T <- Exp(xi) T, with Exp in L[0..16) and the product in H[0..16) (both free now)
-    double P[16];   // the current pose (its 16 loads issued together)
+    double P[16];   // the current pose
 #pragma unroll
-    for (int i = 0; i < 16; ++i) P[i] = st->pose[i];
+    for (int i = 0; i < 16; ++i) P[i] = pre[i];
     double* E = L;
     double* T = H;
     exp_se3(xi, E);
@@ -601,6 +654,10 @@ __device__ __noinline__ void solve_update(const double* v, RegState* st, double*
     }
 }
 
+__device__ __noinline__ void solve_update(const double* v, const double* pre, RegState* st, double* H, double* L) {
+    solve_update_inl(v, pre, st, H, L);
+}
+
 namespace {
 
 constexpr int kSolveThreads = 512;
@@ -610,40 +667,60 @@ constexpr int kSolveParts = 32;
 
 // Reduction of `nparts` FP64 partials (29 values each) in a fixed order, then
 // (thread 0) the 6x6 Cholesky solve, the SE(3) update and the convergence
-// test.  Called by all kSolveThreads threads of one workgroup.
-__device__ void solve_state(const double* __restrict__ partials, int nparts, RegState* __restrict__ st) {
+// test.  Called by all NT threads of one workgroup.
+//
+// The order: task (p, j), p < kSolveParts, sums value j of the partials p,
+// p + 32, p + 64, ... in that order; then value j is the sum of the tasks'
+// results in order of p.  Task q = p * 29 + j reads partials[q + 928 m] for
+// m = 0, 1, ..., so the consecutive tasks of a wavefront read one contiguous
+// span per load instruction.  A thread takes its tasks two at a time and
+// issues KU loads for each before adding any: the partials come from other
+// compute units' caches, so the rounds of loads set the time.  Both the FP32
+// and the FP64 sums are formed (no branch on the accumulation mode ahead of
+// the loads) and the mode picks one.  The result does not depend on NT or KU.
+template <int NT, int KU>
+__device__ __forceinline__ void solve_state(const double* __restrict__ partials, int nparts,
+                                            RegState* __restrict__ st) {
+    static_assert(NT >= kPreFields && NT >= kNumAcc, "solve block size");
     __shared__ double s_part[kNumAcc][kSolveParts];
     __shared__ double s_v[kNumAcc];
+    __shared__ double s_pre[kPreFields];
     __shared__ double s_HL[72];
-    const int acc = st->acc;
+    constexpr int kTasks = kNumAcc * kSolveParts;
     const int t = threadIdx.x;
-    // kNumAcc x kSolveParts strided partial sums, whatever the block size, so
-    // that every caller reduces in the same order
-    // (eight partials are loaded together and then added in order: the
-    // partials come from other compute units' caches, and one dependent load
-    // per addition would serialise their latency)
-    constexpr int kU = 8;
-    for (int q = t; q < kNumAcc * kSolveParts; q += blockDim.x) {
-        const int j = q / kSolveParts, p = q % kSolveParts;
-        float f = 0.f;
-        double v = 0.0;
-        for (int b0 = p; b0 < nparts; b0 += kU * kSolveParts) {
-            double x[kU];
+    // the update's state words (loaded now, stored to LDS after the loop)
+    const double pre = t < kPreFields ? gload((const double*)st, pre_word(t)) : 0.0;
+    const int acc = gload(&st->acc, 0);
+    for (int qa = t; qa < kTasks; qa += 2 * NT) {
+        const int qb = qa + NT;
+        const bool hb = qb < kTasks;
+        const int pa = qa / kNumAcc, pb = hb ? qb / kNumAcc : pa;   // pb >= pa
+        double va = 0.0, vb = 0.0;
+        float fa = 0.f, fb = 0.f;
+        for (int m0 = 0; pa + kSolveParts * m0 < nparts; m0 += KU) {
+            double xa[KU], xb[KU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int b = b0 + u * kSolveParts;
-                x[u] = b < nparts ? partials[(int64_t)b * kNumAcc + j] : 0.0;
+            for (int u = 0; u < KU; ++u) {
+                const int64_t m = m0 + u;
+                xa[u] = pa + kSolveParts * m < nparts ? gload(partials, qa + kTasks * m) : 0.0;
+                xb[u] = hb && pb + kSolveParts * m < nparts ? gload(partials, qb + kTasks * m) : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (b0 + u * kSolveParts < nparts) {
-                    if (acc == GICP_ACC_FP32) f += (float)x[u];
-                    else v += x[u];
+            for (int u = 0; u < KU; ++u) {
+                if (pa + kSolveParts * (m0 + u) < nparts) {
+                    fa += (float)xa[u];
+                    va += xa[u];
+                }
+                if (hb && pb + kSolveParts * (m0 + u) < nparts) {
+                    fb += (float)xb[u];
+                    vb += xb[u];
                 }
             }
         }
-        s_part[j][p] = acc == GICP_ACC_FP32 ? (double)f : v;
+        s_part[qa % kNumAcc][pa] = acc == GICP_ACC_FP32 ? (double)fa : va;
+        if (hb) s_part[qb % kNumAcc][pb] = acc == GICP_ACC_FP32 ? (double)fb : vb;
     }
+    if (t < kPreFields) s_pre[t] = pre;
     __syncthreads();
     if (t < kNumAcc) {
         if (acc == GICP_ACC_FP32) {
@@ -657,8 +734,14 @@ __device__ void solve_state(const double* __restrict__ partials, int nparts, Reg
         }
     }
     __syncthreads();
-    if (t == 0) solve_update(s_v, st, s_HL, s_HL + 36);
+    if (t == 0) solve_update(s_v, s_pre, st, s_HL, s_HL + 36);
     __syncthreads();
+}
+
+// The solve kernels' form: kSolveThreads threads, 20 loads in flight per task.
+__device__ __forceinline__ void solve_block(const double* __restrict__ partials, int nparts,
+                                            RegState* __restrict__ st) {
+    solve_state<kSolveThreads, 20>(partials, nparts, st);
 }
 
 namespace {
@@ -666,7 +749,7 @@ namespace {
 __global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __restrict__ partials, int nblocks,
                                                             RegState* __restrict__ st) {
     if (st->done) return;
-    solve_state(partials, nblocks, st);
+    solve_block(partials, nblocks, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -730,7 +813,8 @@ __global__ __launch_bounds__(kBlock) void k_gn_queue(const ProbDev* __restrict__
         __syncthreads();
         if (s_last) {
             __threadfence();  // acquire the other chunks' partials
-            solve_state(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
+            // (few loads in flight: this kernel's register budget is the linearisation's)
+            solve_state<kBlock, 4>(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
             if (threadIdx.x == 0) {
                 atomicExch(&arrive[p], 0u);
                 __threadfence();  // release the new state before it is announced
@@ -815,7 +899,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_batch(const ProbDev*
                                                                   int32_t* __restrict__ chunk_prob) {
     const ProbDev P = probs[blockIdx.x];
     if (P.st->done) return;
-    solve_state(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, P.st);
+    solve_block(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, P.st);
     __syncthreads();
     // a problem that finished leaves the linearisation grid: its work items
     // exit on their first load in the remaining launches
@@ -887,7 +971,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_track(const ProbDev*
     if (p < 0) return;
     const ProbDev P = probs[p];
     if (P.st->done) return;
-    solve_state(partials, P.nchunks, P.st);
+    solve_block(partials, P.nchunks, P.st);
     __syncthreads();
     if (P.st->done)
         for (int c = threadIdx.x; c < P.nchunks; c += blockDim.x) chunk_prob[c] = -1;
@@ -895,55 +979,162 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve_track(const ProbDev*
 
 // ---------------------------------------------------------------------------
 // Iteration slots: the default form of sequential tracking.  The host
-// launches (linearise, solve) pairs without knowing which problem each pair
-// serves: the device's `cur` names it.  When a problem finishes (converged,
-// max_it, or failed), its solve predicts the next problem's pose and advances
-// `cur`, so the next pair already works on the next problem: a problem costs
-// exactly its own iterations, with no launches after it converges.  The solve
-// also publishes its progress (problems finished, slots run) to host-mapped
-// memory, from which the host decides how many more pairs to launch.
+// launches iterations without knowing which problem each serves: the
+// device's `cur` names it.  One launch is a whole Gauss-Newton iteration:
+// every workgroup linearises its chunk at the current pose and writes its
+// partial; the last workgroup to finish a group of partials (p, p + 32,
+// p + 64, ...) sums that group, and the last group to finish sums the
+// groups and solves; in exactly the order of solve_state, so that the
+// result is bitwise that of the other forms.  When a problem finishes
+// (converged, max_it, or failed), its solve predicts the next problem's pose
+// and advances `cur`, so the next launch already works on the next problem:
+// a problem costs exactly its own iterations.  The solving workgroup also
+// publishes the progress (problems finished, slots run) to host-mapped
+// memory, from which the host decides how many more slots to launch.
 // ---------------------------------------------------------------------------
-template <int ACC, int G>
-__global__ __launch_bounds__(kChunk * G) void k_slot_linearize(const ProbDev* __restrict__ probs, int nprob,
-                                                             const int32_t* __restrict__ cur,
-                                                             double* __restrict__ partials) {
-    const int i = *cur;
-    if (i >= nprob) return;
-    const ProbDev P = probs[i];
-    if ((int)blockIdx.x >= P.nchunks) return;
-    const RegState* st = P.st;
-    if (st->done) return;
-    float R[9], t[3];
+// Per-call hand-over words of the iteration slots (zero between launches).
+struct SlotSync {
+    uint32_t group[kSolveParts];   // partials of group p written so far
+    uint32_t groups;               // groups summed so far
+    uint32_t pad[31];
+    double gsum[kSolveParts][kNumAcc];
+};
+static_assert(sizeof(SlotSync) % 8 == 0, "slot words");
+
+// Members of group p among nparts partials.
+__device__ __forceinline__ int group_members(int p, int nparts) { return p < nparts ? (nparts - p + 31) / 32 : 0; }
+
+// Thread j < 29 of an NT-thread workgroup returns value j of group p's sum
+// (partials p + 32 m in order of m; FP32 or FP64 as the mode), read
+// device-coherently and staged through s_rows (LDS) 64 partials at a time.
+constexpr int kGroupRows = 64;
+template <int NT>
+__device__ __forceinline__ double group_sum(const double* __restrict__ partials, int p, int nparts, int acc,
+                                            double (*s_rows)[kNumAcc]) {
+    constexpr int kRows = kGroupRows;
+    constexpr int kPer = (kRows * kNumAcc + NT - 1) / NT;
+    const int t = threadIdx.x;
+    const int members = group_members(p, nparts);
+    double v = 0.0;
+    float f = 0.f;
+    for (int m0 = 0; m0 < members; m0 += kRows) {
+        const int cnt = min(kRows, members - m0);
+        double x[kPer];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+        for (int u = 0; u < kPer; ++u) {
+            const int e = t + u * NT, mm = e / kNumAcc, j = e % kNumAcc;
+            x[u] = mm < cnt ? load_dev(&partials[(int64_t)(p + kSolveParts * (m0 + mm)) * kNumAcc + j]) : 0.0;
+        }
 #pragma unroll
-    for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
-    chunk_linearize<ACC, G>(P, blockIdx.x, R, t, partials + (int64_t)blockIdx.x * kNumAcc);
+        for (int u = 0; u < kPer; ++u) {
+            const int e = t + u * NT;
+            if (e < kRows * kNumAcc) s_rows[e / kNumAcc][e % kNumAcc] = x[u];
+        }
+        __syncthreads();
+        if (t < kNumAcc)
+            for (int mm = 0; mm < cnt; ++mm) {
+                f += (float)s_rows[mm][t];
+                v += s_rows[mm][t];
+            }
+        __syncthreads();
+    }
+    return acc == GICP_ACC_FP32 ? (double)f : v;
 }
 
-// ctl (device): [0] the current problem, [1] slots run.
-__global__ __launch_bounds__(kSolveThreads) void k_slot_solve(const ProbDev* __restrict__ probs, int nprob,
-                                                              const double* __restrict__ partials,
-                                                              int32_t* __restrict__ ctl, int motion,
-                                                              int32_t* __restrict__ progress) {
-    const int i = ctl[0];
-    const int slots = ctl[1] + 1;
+// ctl (device): [0] and [1] the current problem for launches of parity 0 and
+// 1 (every workgroup of a launch reads its own word, which only the next
+// launch's parity is written to: workgroups that start late still see the
+// launch's problem), [2] slots run.  The kernel's registers are bounded so
+// that five workgroups fit on a CU: a 77k-point frame's chunks all resident.
+template <int ACC, int G>
+__global__ __launch_bounds__(kChunk * G) __attribute__((amdgpu_waves_per_eu(5))) void k_slot_iterate(
+    const ProbDev* __restrict__ probs, int nprob, int32_t* __restrict__ ctl, int parity, double* __restrict__ partials,
+    SlotSync* __restrict__ sync, int motion, int32_t* __restrict__ progress) {
+    constexpr int NT = kChunk * G;
+    static_assert(NT >= kNumAcc && NT >= kPreFields && NT > kSolveParts, "slot block size");
+    static_assert(kGroupRows >= kSolveParts, "the group rows also hold the groups' sums");
+    __shared__ int s_last;
+    __shared__ double s_rows[kGroupRows][kNumAcc];
+    __shared__ double s_v[kNumAcc];
+    __shared__ double s_pre[kPreFields];
+    __shared__ double s_HL[72];
+    const int t = threadIdx.x;
+    const int b = blockIdx.x;
+    const int i = ctl[parity];
+    bool solver = false;   // this workgroup completes the launch
     if (i < nprob) {
         const ProbDev P = probs[i];
-        if (!P.st->done) solve_state(partials, P.nchunks, P.st);
-        __syncthreads();
-        if (threadIdx.x == 0 && P.st->done) {
-            if (i + 1 < nprob) predict_pose(probs, i + 1, motion);
-            ctl[0] = i + 1;
+        RegState* st = P.st;
+        if (st->done) {
+            solver = b == 0;   // finished before its first iteration: only move on
+        } else {
+            if (b >= P.nchunks) return;
+            float R[9], tr[3];
+#pragma unroll
+            for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) tr[j] = st->tf[j];
+            chunk_linearize<ACC, G, true>(P, b, R, tr, partials + (int64_t)b * kNumAcc);
+            const int p = b % kSolveParts;
+            if (t == 0)
+                s_last = atomicAdd(&sync->group[p], 1u) == (uint32_t)group_members(p, P.nchunks) - 1u ? 1 : 0;
+            __syncthreads();
+            if (!s_last) return;
+            handover_acquire();
+            const int acc = st->acc;
+            const double gs = group_sum<NT>(partials, p, P.nchunks, acc, s_rows);
+            if (t < kNumAcc) {
+                store_dev(&sync->gsum[p][t], gs);
+                handover_release();
+            }
+            __syncthreads();
+            const int ngroups = min(kSolveParts, P.nchunks);
+            if (t == 0) s_last = atomicAdd(&sync->groups, 1u) == (uint32_t)ngroups - 1u ? 1 : 0;
+            __syncthreads();
+            if (!s_last) return;
+            handover_acquire();
+            // the last group: the groups' sums in order of p (empty groups
+            // add zero, as in solve_state), then the update
+            const double pre = t < kPreFields ? gload((const double*)st, pre_word(t)) : 0.0;
+            for (int e = t; e < ngroups * kNumAcc; e += NT)
+                s_rows[e / kNumAcc][e % kNumAcc] = load_dev(&sync->gsum[0][0] + e);
+            if (t < kPreFields) s_pre[t] = pre;
+            __syncthreads();
+            if (t < kNumAcc) {
+                if (acc == GICP_ACC_FP32) {
+                    float f = 0.f;
+                    for (int q = 0; q < kSolveParts; ++q) f += q < ngroups ? (float)s_rows[q][t] : 0.f;
+                    s_v[t] = (double)f;
+                } else {
+                    double v = 0.0;
+                    for (int q = 0; q < kSolveParts; ++q) v += q < ngroups ? s_rows[q][t] : 0.0;
+                    s_v[t] = v;
+                }
+            }
+            // the hand-over words back to zero for the next launch
+            if (t < kSolveParts) __hip_atomic_store(&sync->group[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == kSolveParts) __hip_atomic_store(&sync->groups, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            if (t == 0) solve_update_inl(s_v, s_pre, st, s_HL, s_HL + 36);
+            __syncthreads();
+            solver = true;
         }
+    } else {
+        solver = b == 0;   // every problem finished: only count the slot
     }
-    if (threadIdx.x == 0) {
-        ctl[1] = slots;
-        // progress for the host (host-mapped memory, plain vector stores)
-        const int done = i < nprob && probs[i].st->done ? i + 1 : (i < nprob ? i : nprob);
-        __hip_atomic_store(&progress[0], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&progress[1], slots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (!solver || t != 0) return;
+    const int slots = ctl[2] + 1;
+    int next = i, done = i < nprob ? i : nprob;
+    if (i < nprob && probs[i].st->done) {
+        if (i + 1 < nprob) predict_pose(probs, i + 1, motion);
+        next = i + 1;
+        done = i + 1;
     }
+    ctl[parity ^ 1] = next;
+    ctl[2] = slots;
+    // progress for the host (host-mapped memory, plain vector stores)
+    __hip_atomic_store(&progress[0], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&progress[1], slots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ---------------------------------------------------------------------------
@@ -1202,29 +1393,27 @@ hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, 
     return hipGetLastError();
 }
 
-hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int64_t grid, double* partials, int acc,
-                             int motion, int32_t* progress, hipStream_t s, bool linearize, bool solve) {
+hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int parity, int64_t grid, double* partials,
+                             int acc, int motion, int32_t* progress, void* sync, hipStream_t s) {
     constexpr int kT = kChunk * kTrackGroup;
-    if (linearize) {
-        switch (acc) {
-            case GICP_ACC_FP32:
-                hipLaunchKernelGGL((k_slot_linearize<GICP_ACC_FP32, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s,
-                                   probs, nprob, (const int32_t*)ctl, partials);
-                break;
-            case GICP_ACC_FP64:
-                hipLaunchKernelGGL((k_slot_linearize<GICP_ACC_FP64, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s,
-                                   probs, nprob, (const int32_t*)ctl, partials);
-                break;
-            default:
-                hipLaunchKernelGGL((k_slot_linearize<GICP_ACC_TWOSUM, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0,
-                                   s, probs, nprob, (const int32_t*)ctl, partials);
-        }
+    SlotSync* sy = (SlotSync*)sync;
+    switch (acc) {
+        case GICP_ACC_FP32:
+            hipLaunchKernelGGL((k_slot_iterate<GICP_ACC_FP32, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s, probs,
+                               nprob, ctl, parity, partials, sy, motion, progress);
+            break;
+        case GICP_ACC_FP64:
+            hipLaunchKernelGGL((k_slot_iterate<GICP_ACC_FP64, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s, probs,
+                               nprob, ctl, parity, partials, sy, motion, progress);
+            break;
+        default:
+            hipLaunchKernelGGL((k_slot_iterate<GICP_ACC_TWOSUM, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s,
+                               probs, nprob, ctl, parity, partials, sy, motion, progress);
     }
-    if (solve)
-        hipLaunchKernelGGL(k_slot_solve, dim3(1), dim3(kSolveThreads), 0, s, probs, nprob, (const double*)partials, ctl,
-                           motion, progress);
     return hipGetLastError();
 }
+
+size_t slot_sync_bytes() { return sizeof(SlotSync); }
 
 hipError_t launch_state_init(const ProbDev& pd, ProbDev* dst, const StateInit& si, const double* init, RegState* st,
                              hipStream_t s) {

@@ -179,11 +179,15 @@ hipError_t launch_state_out(const RegState* st, const int* err, double* pose, do
 // pose, then its iterations over a grid of the largest problem's chunks.
 hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter, int32_t* chunk_prob, int64_t grid,
                               int motion, hipStream_t s);
-// One iteration slot of sequential tracking.  ctl: device int32[2] (the
-// current problem, slots run; zero before the first slot); progress:
-// host-mapped int32[2] receiving (problems finished, slots run).
-hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int64_t grid, double* partials, int acc,
-                             int motion, int32_t* progress, hipStream_t s, bool linearize, bool solve);
+// One iteration slot of sequential tracking (one launch: linearisation,
+// reduction and solve).  ctl: device int32[3] (the current problem for
+// launches of parity 0 and 1, slots run; zero before the first slot); parity:
+// the launch's index modulo 2; progress: host-mapped int32[2] receiving
+// (problems finished, slots run); sync: slot_sync_bytes() of device memory,
+// zero before the first slot (each slot leaves it zero).
+hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int parity, int64_t grid, double* partials,
+                             int acc, int motion, int32_t* progress, void* sync, hipStream_t s);
+size_t slot_sync_bytes();
 hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, int64_t grid, double* partials, int acc,
                                      bool linearize, bool solve, hipStream_t s);
 

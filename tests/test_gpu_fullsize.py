@@ -284,9 +284,11 @@ def test_c4_no_reuse_bitwise(g, ctx, c4):
 
 @pytest.mark.parametrize("motion", [0, 1])
 def test_c2_track_closed_loop_vs_oracle(g, ctx, c2, motion):
-    """The first 12 frames tracked in one gicp_track call (graph-replayed, the
+    """The first 12 frames tracked in one gicp_track call (iteration slots, the
     timed form), each frame from the pose predicted from its own previous
-    estimates, against the oracle's tracking loop with the same motion model."""
+    estimates, against the oracle's tracking loop with the same motion model;
+    the graph-replayed form bitwise equal (frames of 1,000+ work items: the
+    slots' two-level hand-over of partials with groups of 30+ members)."""
     from scipy.spatial import cKDTree
 
     from oracle import tracking as ot
@@ -294,10 +296,15 @@ def test_c2_track_closed_loop_vs_oracle(g, ctx, c2, motion):
     n = 12
     src_cell = ctx.estimate_cell(frames[0], 20)
     prm = g.params(k=20, eps=1e-3, r_max=R_MAX, max_it=MAX_IT, conv_rot=CONV, conv_trans=CONV,
-                   reg_mode=g.REG_PLANE, cell_src=src_cell, flags=g.FLAG_GRAPH)
+                   reg_mode=g.REG_PLANE, cell_src=src_cell)
     _say("c2 track", motion)
     res = ctx.track(frames[:n], gm, seq.poses[0], motion=motion, prm=prm)
     assert all(r.status == 0 for r in res)
+    prm.flags = g.FLAG_GRAPH
+    res_g = ctx.track(frames[:n], gm, seq.poses[0], motion=motion, prm=prm)
+    for a, b in zip(res, res_g):
+        assert np.array_equal(a.pose, b.pose) and np.array_equal(a.H, b.H) and np.array_equal(a.b, b.b)
+        assert a.iters == b.iters and a.status == b.status
     map_cov = oc.regularise6(seq.map_cov_raw, oc.REG_PLANE, 1e-3)
     tree = cKDTree(seq.map_means.astype(np.float64))
     est, _, ores = ot.track([seq.frame(i) for i in range(n)], seq.map_means, map_cov, seq.poses[0],

@@ -68,7 +68,7 @@ def test_track_vs_oracle(env, motion):
 def test_track_equals_register_from_same_inits(env, motion):
     """Every frame of the tracked sequence against gicp_register started from
     the pose the host predicts from the tracked estimates (the first frame
-    bitwise); the persistent (default), launched and graph-replayed forms
+    bitwise); the iteration-slot (default), launched and graph-replayed forms
     bitwise equal."""
     g, ctx = env
     mp, mc, frames, poses = _sequence(seed=5)
