@@ -40,16 +40,20 @@ BYTES_PER_UNIT = {
     3: 232.0,  # solve: 29 FP64 partials per ... (negligible)
 }
 GROUP_NAMES = {0: "k_gn_linearize", 1: "k_knn_cov", 2: "grid build (keys, radix sort, table)", 3: "k_gn_solve"}
+# In the tracking form one launch is a whole iteration (group 0): the
+# linearisation, the hand-over of the partials and the solve.
+TRACK_NAMES = {**GROUP_NAMES, 0: "k_slot_iterate"}
 # Calibrated HBM bytes per unit from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
-# the tracking form on this workload (profiles/hbm_traffic__c2_track_pmc.md):
-# linearisation per point and iteration over the launches that did work.
+# the tracking form on this workload
+# (profiles/hbm_traffic__k_slot_iterate__c2_track_pmc.md): per point and
+# iteration over the launches that did work.
 # Valid for the kernels as they were when the counters were taken (None: not
 # taken for the current kernels).
-TRAFFIC_BYTES_PER_UNIT = {0: 305.1}
+TRAFFIC_BYTES_PER_UNIT = {0: 313.4}
 # Wavefront VALU instructions per unit from rocprofv3 SQ_INSTS_VALU on the same
-# runs (profiles/hbm_traffic__c2_track_pmc.md), and the chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64
+# runs (profiles/hbm_traffic__k_slot_iterate__c2_track_pmc.md), and the chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64
 # instruction per SIMD every 4 cycles (16 lanes a cycle) at 2.4 GHz.
-VALU_INSTS_PER_UNIT = {0: 127.3}
+VALU_INSTS_PER_UNIT = {0: 129.0}
 VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
 MOTION_NAMES = {0: "previous", 1: "constant_velocity"}
 
@@ -134,21 +138,21 @@ def copy_calibration(mib):
     log(f"copied {mib} MiB five times")
 
 
-def kernel_table(prof, frames):
+def kernel_table(prof, frames, names=GROUP_NAMES):
     out = {}
     for gid, (n, ms, units) in prof.items():
         if n == 0:
             continue
-        out[GROUP_NAMES[gid]] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms_per_frame": ms / frames,
-                                 "units_per_launch": units / n}
+        out[names[gid]] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms_per_frame": ms / frames,
+                           "units_per_launch": units / n}
     return out
 
 
-def roofline_of(prof, gid):
+def roofline_of(prof, gid, names=GROUP_NAMES):
     n, ms, units = prof[gid]
     achieved = BYTES_PER_UNIT[gid] * units / (ms * 1e-3) / 1e9
     traffic = TRAFFIC_BYTES_PER_UNIT.get(gid)
-    r = {"kernel": GROUP_NAMES[gid], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    r = {"kernel": names[gid], "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
          "traffic": None if traffic is None else round(traffic * units / n),
          "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
@@ -282,8 +286,8 @@ def main():
     el_ev, _ = timed(lambda: ctx.track(frames[:K], gmap, T0, motion, prm(0)))
     prof = {gid: ctx.profile_read(gid) for gid in range(4)}
     ctx.profile(False)
-    kernels = kernel_table(prof, K)
-    roofline = roofline_of(prof, 0)
+    kernels = kernel_table(prof, K, TRACK_NAMES)
+    roofline = roofline_of(prof, 0, TRACK_NAMES)
 
     # --- secondary forms on the same frames
     # per-frame form: one gicp_register call per frame, closed on the previous estimate
@@ -349,9 +353,9 @@ def main():
                                f"{nf}-frame trajectory, k=20, plane eps=1e-3, r_max=0.1 m, <=20 GN it",
                    "frames": K, "map_gaussians": args.map_size, "mean_points": float(npts[:K].mean()),
                    "form": f"gicp_track: one call for the {K} frames; frame covariances in batched launches, "
-                           "then (linearise, solve) launch pairs whose frame the device picks: a frame's last "
-                           "solve predicts the next frame's pose from the estimates and moves on to it; a step "
-                           "is one frame",
+                           "then one launch per Gauss-Newton iteration (linearisation, device-side hand-over "
+                           "of the partials, solve) whose frame the device picks: a frame's last solve predicts "
+                           "the next frame's pose from the estimates and moves on to it; a step is one frame",
                    "motion": MOTION_NAMES[motion], "init": "frame 0 from its ground-truth pose"},
         "tracking": {"statuses": statuses, "mean_gn_iterations": float(np.mean(iters)),
                      "value_with_kernel_events": round(K / el_ev, 3),
