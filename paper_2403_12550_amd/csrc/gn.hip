@@ -292,6 +292,62 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
     return res;
 }
 
+// Hand-over of values between workgroups of one launch without cache
+// write-back.  An agent-scope fence writes back the whole L2 of the XCD
+// (measured: a launch of 1,057 workgroups that each fence before a counter
+// update takes 110 us against 44 us without), so the values handed over are
+// written and read with agent-scope (device-coherent) atomic accesses, and the
+// hand-over only orders them: the writer waits for its stores to complete
+// before the counter update, and the reader's loads are not moved above the
+// counter update.
+__device__ __forceinline__ void store_dev(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_dev(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt with vmcnt = 0 and the other counters left alone (gfx9 encoding)
+constexpr int kWaitVm0 = (0x7 << 4) | (0xf << 8);
+__device__ __forceinline__ void handover_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+}
+__device__ __forceinline__ void handover_acquire() {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// A value written (read) by one workgroup for others of the same launch:
+// device-coherent when DEV, plain otherwise.
+template <bool DEV, typename T>
+__device__ __forceinline__ void sput(T* p, T v) {
+    if (DEV) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <bool DEV, typename T>
+__device__ __forceinline__ T sget(const T* p) {
+    if (DEV) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+// A float4 as two device-coherent 8-byte words.
+__device__ __forceinline__ float4 load4_dev(const float4* p) {
+    const uint64_t* q = (const uint64_t*)p;
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float4 r;
+    __builtin_memcpy(&r.x, &a, 8);
+    __builtin_memcpy(&r.z, &b, 8);
+    return r;
+}
+__device__ __forceinline__ void store4_dev(float4* p, float4 v) {
+    uint64_t a, b;
+    __builtin_memcpy(&a, &v.x, 8);
+    __builtin_memcpy(&b, &v.z, 8);
+    uint64_t* q = (uint64_t*)p;
+    __hip_atomic_store(q, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Linearisation of source point i at the pose (R, t), evaluated by a group of
 // G lanes (lane l of the group): on return, v[0..29) holds the point's
 // 21 unique terms of J^T M J, the 6 of J^T M d, d^T M d and 1 (the inlier
@@ -299,7 +355,7 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
 // correspondence within r_max or a singular combined covariance.
 // Point i of the problem's processing order: the grid-cell order when the
 // problem carries its sorted source (ssrc, sscov), else the caller's order.
-template <int G>
+template <int G, bool COH = false>
 __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, const float* R, const float* t,
                                                 float* v, int l) {
     const int64_t n = P.n;
@@ -325,10 +381,10 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     // its search certified (the nearest mean cannot have changed); otherwise
     // search again, starting from that match (unless every search is to
     // start afresh)
-    const int32_t hint = P.fresh ? -1 : gload((const int32_t*)P.nn_prev, i);
+    const int32_t hint = P.fresh ? -1 : (COH ? sget<true>(P.nn_prev + i) : gload((const int32_t*)P.nn_prev, i));
     bool reuse = false;
     if (hint >= 0) {
-        const float4 cq = gload((const float4*)P.nn_cache, i);
+        const float4 cq = COH ? load4_dev(P.nn_cache + i) : gload((const float4*)P.nn_cache, i);
         const float ex = qx - cq.x, ey = qy - cq.y, ez = qz - cq.z;
         reuse = sqrtf(ex * ex + ey * ey + ez * ez) < cq.w;
     }
@@ -340,8 +396,13 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
         float free_r;
         pos = nearest<true, G>(map, qx, qy, qz, l, hint, &free_r);
         if (l == 0) {
-            gstore(P.nn_prev, i, pos);
-            gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
+            if (COH) {
+                sput<true>(P.nn_prev + i, pos);
+                store4_dev(P.nn_cache + i, make_float4(qx, qy, qz, free_r));
+            } else {
+                gstore(P.nn_prev, i, pos);
+                gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
+            }
         }
     }
     if (pos < 0) return false;
@@ -414,38 +475,15 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
     return true;
 }
 
-// Hand-over of values between workgroups of one launch without cache
-// write-back.  An agent-scope fence writes back the whole L2 of the XCD
-// (measured: a launch of 1,057 workgroups that each fence before a counter
-// update takes 110 us against 44 us without), so the values handed over are
-// written and read with agent-scope (device-coherent) atomic accesses, and the
-// hand-over only orders them: the writer waits for its stores to complete
-// before the counter update, and the reader's loads are not moved above the
-// counter update.
-__device__ __forceinline__ void store_dev(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_dev(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// s_waitcnt with vmcnt = 0 and the other counters left alone (gfx9 encoding)
-constexpr int kWaitVm0 = (0x7 << 4) | (0xf << 8);
-__device__ __forceinline__ void handover_release() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-}
-__device__ __forceinline__ void handover_acquire() {
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, G
 // lanes per point.  The group's first lane stores the point's 29 values in an
 // LDS row (zeros when it is not an inlier); threads 0..28 then sum one column
 // each over the 64 rows in a fixed order, and write the chunk's FP64 partial
 // (with DEV device-coherently, completed before the closing barrier, for a
-// hand-over within the launch).
-template <int ACC, int G = kGroup, bool DEV = false>
+// hand-over within the launch; with COH also the points' reuse state, for
+// a launch in which another workgroup may take the chunk's next iteration).
+template <int ACC, int G = kGroup, bool DEV = false, bool COH = false>
 __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, const float* R, const float* t,
                                                 double* __restrict__ out) {
     __shared__ float s_val[kChunk][kNumAcc + 1];
@@ -454,11 +492,12 @@ __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, con
     const int64_t i = c * kChunk + pt;
     float v[kNumAcc];
     bool ok = false;
-    if (i < P.n) ok = linearize_point<G>(P, i, R, t, v, l);
+    if (i < P.n) ok = linearize_point<G, COH>(P, i, R, t, v, l);
     if (l == 0) {
 #pragma unroll
         for (int j = 0; j < kNumAcc; ++j) s_val[pt][j] = ok ? v[j] : 0.f;
     }
+    if (COH) handover_release();
     __syncthreads();
     if (threadIdx.x < kNumAcc * kSumParts) {
         const int col = threadIdx.x / kSumParts, part = threadIdx.x % kSumParts;
@@ -553,6 +592,7 @@ __device__ __forceinline__ int pre_word(int t) {
 // kernel bounds its registers (the iteration slots); called through
 // solve_update elsewhere, so that the single-thread FP64 code does not raise
 // the register footprint of the kernels that embed it.
+template <bool DEV = false>
 __device__ __forceinline__ void solve_update_inl(const double* v, const double* pre, RegState* st, double* H,
                                                  double* L) {
     int32_t im[2];
@@ -567,14 +607,14 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
             H[6 * j + i] = v[q];
             ++q;
         }
-    for (int j = 0; j < 21; ++j) st->H[j] = v[j];
-    for (int j = 0; j < 6; ++j) st->b[j] = v[21 + j];
-    st->cost = v[27];
-    st->n_inl = v[28];
-    st->iters = iters;
+    for (int j = 0; j < 21; ++j) sput<DEV>(&st->H[j], v[j]);
+    for (int j = 0; j < 6; ++j) sput<DEV>(&st->b[j], v[21 + j]);
+    sput<DEV>(&st->cost, v[27]);
+    sput<DEV>(&st->n_inl, v[28]);
+    sput<DEV>(&st->iters, iters);
     if (v[28] < 6.0) {
-        st->status = GICP_E_NO_CORR;
-        st->done = 1;
+        sput<DEV>(&st->status, (int32_t)GICP_E_NO_CORR);
+        sput<DEV>(&st->done, 1);
         return;
     }
     // Cholesky H = L L^T; a pivot not above 1e-12 * max(diag H) fails.  The
@@ -594,8 +634,8 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= Lr[6 * j + k] * Lr[6 * j + k];
         if (!(s > floor_) || !isfinite(s)) {
-            st->status = GICP_E_DEGENERATE;
-            st->done = 1;
+            sput<DEV>(&st->status, (int32_t)GICP_E_DEGENERATE);
+            sput<DEV>(&st->done, 1);
             return;
         }
         Lr[7 * j] = sqrt(s);
@@ -639,19 +679,25 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
             for (int k = 0; k < 4; ++k) s += E[4 * i + k] * P[4 * k + j];
             T[4 * i + j] = s;
         }
-    for (int i = 0; i < 16; ++i) st->pose[i] = T[i];
+    for (int i = 0; i < 16; ++i) sput<DEV>(&st->pose[i], T[i]);
     const double nw = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
     const double nv = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
     if (nw < conv_rot && nv < conv_trans) {
-        st->converged = 1;
-        st->done = 1;
+        sput<DEV>(&st->converged, 1);
+        sput<DEV>(&st->done, 1);
     } else if (iters >= max_it) {
-        st->done = 1;
+        sput<DEV>(&st->done, 1);
     }
     for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 3; ++j) st->Rf[3 * i + j] = (float)T[4 * i + j];
-        st->tf[i] = (float)T[4 * i + 3];
+        for (int j = 0; j < 3; ++j) sput<DEV>(&st->Rf[3 * i + j], (float)T[4 * i + j]);
+        sput<DEV>(&st->tf[i], (float)T[4 * i + 3]);
     }
+}
+
+// The update with device-coherent stores (read by other workgroups of a
+// persistent launch).
+__device__ __noinline__ void solve_update_dev(const double* v, const double* pre, RegState* st, double* H, double* L) {
+    solve_update_inl<true>(v, pre, st, H, L);
 }
 
 __device__ __noinline__ void solve_update(const double* v, const double* pre, RegState* st, double* H, double* L) {
@@ -678,7 +724,7 @@ constexpr int kSolveParts = 32;
 // compute units' caches, so the rounds of loads set the time.  Both the FP32
 // and the FP64 sums are formed (no branch on the accumulation mode ahead of
 // the loads) and the mode picks one.  The result does not depend on NT or KU.
-template <int NT, int KU>
+template <int NT, int KU, bool DEV = false>
 __device__ __forceinline__ void solve_state(const double* __restrict__ partials, int nparts,
                                             RegState* __restrict__ st) {
     static_assert(NT >= kPreFields && NT >= kNumAcc, "solve block size");
@@ -689,7 +735,9 @@ __device__ __forceinline__ void solve_state(const double* __restrict__ partials,
     constexpr int kTasks = kNumAcc * kSolveParts;
     const int t = threadIdx.x;
     // the update's state words (loaded now, stored to LDS after the loop)
-    const double pre = t < kPreFields ? gload((const double*)st, pre_word(t)) : 0.0;
+    const double pre =
+        t < kPreFields ? (DEV ? sget<true>((const double*)st + pre_word(t)) : gload((const double*)st, pre_word(t)))
+                       : 0.0;
     const int acc = gload(&st->acc, 0);
     for (int qa = t; qa < kTasks; qa += 2 * NT) {
         const int qb = qa + NT;
@@ -702,8 +750,12 @@ __device__ __forceinline__ void solve_state(const double* __restrict__ partials,
 #pragma unroll
             for (int u = 0; u < KU; ++u) {
                 const int64_t m = m0 + u;
-                xa[u] = pa + kSolveParts * m < nparts ? gload(partials, qa + kTasks * m) : 0.0;
-                xb[u] = hb && pb + kSolveParts * m < nparts ? gload(partials, qb + kTasks * m) : 0.0;
+                xa[u] = pa + kSolveParts * m < nparts ? (DEV ? load_dev(partials + qa + kTasks * m)
+                                                             : gload(partials, qa + kTasks * m))
+                                                      : 0.0;
+                xb[u] = hb && pb + kSolveParts * m < nparts ? (DEV ? load_dev(partials + qb + kTasks * m)
+                                                                   : gload(partials, qb + kTasks * m))
+                                                            : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < KU; ++u) {
@@ -734,7 +786,10 @@ __device__ __forceinline__ void solve_state(const double* __restrict__ partials,
         }
     }
     __syncthreads();
-    if (t == 0) solve_update(s_v, s_pre, st, s_HL, s_HL + 36);
+    if (t == 0) {
+        if (DEV) solve_update_dev(s_v, s_pre, st, s_HL, s_HL + 36);
+        else solve_update(s_v, s_pre, st, s_HL, s_HL + 36);
+    }
     __syncthreads();
 }
 
@@ -764,12 +819,18 @@ __global__ __launch_bounds__(kSolveThreads) void k_gn_solve(const double* __rest
 // ---------------------------------------------------------------------------
 constexpr long long kSpinLimit = 1ll << 24;
 
+// A value equal on every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// (registers bounded so that five workgroups fit on a CU)
 template <int ACC>
-__global__ __launch_bounds__(kBlock) void k_gn_queue(const ProbDev* __restrict__ probs, QueueDev* __restrict__ q,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_gn_queue(const ProbDev* __restrict__ probs, QueueDev* __restrict__ q,
                                                      uint32_t* __restrict__ items, uint32_t* __restrict__ arrive,
                                                      double* __restrict__ partials) {
     __shared__ uint32_t s_item;
@@ -796,29 +857,31 @@ __global__ __launch_bounds__(kBlock) void k_gn_queue(const ProbDev* __restrict__
         __syncthreads();
         const uint32_t item = s_item;
         if (item == 0u) return;
-        __threadfence();  // acquire: the problem's state as of the push of this item
+        // the problem's state as of the push of this item: written by
+        // another workgroup of this launch, read device-coherently (the
+        // hand-overs below order, rather than fence, the values they pass:
+        // an agent-scope fence would write back this XCD's whole L2 for
+        // every item)
+        handover_acquire();
         const uint32_t p = (item - 1u) >> kChunkBits, c = (item - 1u) & ((1u << kChunkBits) - 1u);
         const ProbDev P = probs[p];
         RegState* st = P.st;
         float R[9], t[3];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) R[j] = st->Rf[j];
+        for (int j = 0; j < 9; ++j) R[j] = uniform(sget<true>(&st->Rf[j]));
 #pragma unroll
-        for (int j = 0; j < 3; ++j) t[j] = st->tf[j];
-        chunk_linearize<ACC>(P, c, R, t, partials + ((int64_t)P.part0 + c) * kNumAcc);
-        if (threadIdx.x == 0) {
-            __threadfence();  // release this chunk's partial
-            s_last = (atomicAdd(&arrive[p], 1u) == (uint32_t)P.nchunks - 1u) ? 1 : 0;
-        }
+        for (int j = 0; j < 3; ++j) t[j] = uniform(sget<true>(&st->tf[j]));
+        chunk_linearize<ACC, kGroup, true, true>(P, c, R, t, partials + ((int64_t)P.part0 + c) * kNumAcc);
+        if (threadIdx.x == 0) s_last = (atomicAdd(&arrive[p], 1u) == (uint32_t)P.nchunks - 1u) ? 1 : 0;
         __syncthreads();
         if (s_last) {
-            __threadfence();  // acquire the other chunks' partials
+            handover_acquire();
             // (few loads in flight: this kernel's register budget is the linearisation's)
-            solve_state<kBlock, 4>(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
+            solve_state<kBlock, 4, true>(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
             if (threadIdx.x == 0) {
                 atomicExch(&arrive[p], 0u);
-                __threadfence();  // release the new state before it is announced
-                if (st->done) {
+                handover_release();   // the new state complete before it is announced
+                if (sget<true>(&st->done)) {
                     s_base = 0xFFFFFFFFu;
                     atomicSub(&q->remaining, 1u);
                 } else {
@@ -828,7 +891,6 @@ __global__ __launch_bounds__(kBlock) void k_gn_queue(const ProbDev* __restrict__
             __syncthreads();
             const uint32_t base = s_base;
             if (base != 0xFFFFFFFFu) {
-                __threadfence();
                 for (int j = threadIdx.x; j < P.nchunks; j += kBlock)
                     if (base + (uint32_t)j < cap)
                         __hip_atomic_store(&items[base + j], ((p << kChunkBits) | (uint32_t)j) + 1u, __ATOMIC_RELAXED,
