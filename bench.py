@@ -256,6 +256,16 @@ def main():
                         reg_mode=g.REG_PLANE, cell_src=src_cell, flags=flags)
 
     T0 = seq.poses[0]
+    # lanes per source point of the tracking launches, chosen by the autotuner
+    # (cached per device and workload size)
+    from paper_2403_12550_amd import autotune
+    lanes, lanes_rec = autotune.tune_track_lanes(ctx, frames[:K], gmap, T0, motion, prm(0))
+    log(f"tracking lanes per point (autotuned): {lanes_rec}")
+
+    def prm(flags=0, lanes=lanes):
+        return g.params(k=20, eps=1e-3, r_max=r_max, max_it=max_it, conv_rot=conv, conv_trans=conv,
+                        reg_mode=g.REG_PLANE, cell_src=src_cell, flags=flags, lanes=lanes)
+
     # --- headline: closed-loop tracking, one gicp_track call for the K frames
     # in its default form (iteration slots: each frame costs its own
     # iterations, the device moves on to the next frame itself)
@@ -294,7 +304,7 @@ def main():
     def per_frame():
         est = []
         for i in range(K):
-            est.append(ctx.register(frames[i], gmap, predict(est, i, T0, motion), prm()).pose)
+            est.append(ctx.register(frames[i], gmap, predict(est, i, T0, motion), prm(lanes=0)).pose)
         return est
     per_frame()
     el_pf, _ = timed(per_frame)
@@ -306,7 +316,7 @@ def main():
         out = []
         for s0 in range(0, K, args.batch):
             idx = list(range(s0, min(K, s0 + args.batch)))
-            out += ctx.register_batch([(frames[i], None, gmap, inits[i]) for i in idx], prm(g.FLAG_GRAPH))
+            out += ctx.register_batch([(frames[i], None, gmap, inits[i]) for i in idx], prm(g.FLAG_GRAPH, lanes=0))
         return out
     batched()
     el_b, _ = timed(batched)
@@ -358,6 +368,7 @@ def main():
                            "the next frame's pose from the estimates and moves on to it; a step is one frame",
                    "motion": MOTION_NAMES[motion], "init": "frame 0 from its ground-truth pose"},
         "tracking": {"statuses": statuses, "mean_gn_iterations": float(np.mean(iters)),
+                     "lanes_per_point": lanes, "lanes_autotune": lanes_rec,
                      "value_with_kernel_events": round(K / el_ev, 3),
                      "per_frame_launch_pairs_form": {"value": round(K / el_launch, 3),
                                                      "form": "max_it (linearise, solve) launch pairs per frame"},
@@ -400,23 +411,30 @@ def run_c4(ctx, g, n_prob=64):
         items.append((g.to_soa(p.src), None, gm, p.init))
     torch.cuda.synchronize()
     log(f"c4: {n_prob} problems generated and maps built in {time.perf_counter() - t0:.1f} s")
+    from paper_2403_12550_amd import autotune
     prm = g.params(k=20, eps=1e-3, r_max=0.1, max_it=30, conv_rot=1e-6, conv_trans=1e-6, reg_mode=g.REG_PLANE)
-    out = {}
-    for name, flags in (("batched", 0), ("queue", g.FLAG_QUEUE), ("per_problem", g.FLAG_MULTI_LAUNCH)):
+    (t_flags, t_lanes), trec = autotune.tune_form(ctx, items, prm)
+    log(f"c4 autotuned form: {trec}")
+    out = {"autotune": trec}
+    for name, flags, lanes in (("batched", 0, 0), ("queue", g.FLAG_QUEUE, 0), ("per_problem", g.FLAG_MULTI_LAUNCH, 0),
+                               ("tuned", t_flags, t_lanes)):
         p2 = g.params(k=20, eps=1e-3, r_max=0.1, max_it=30, conv_rot=1e-6, conv_trans=1e-6, reg_mode=g.REG_PLANE,
-                      flags=flags)
+                      flags=flags, lanes=lanes)
         ctx.register_batch(items, p2)
         torch.cuda.synchronize()
-        ctx.profile(True)
         t = time.perf_counter()
         res = ctx.register_batch(items, p2)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
+        # kernel times from a second, evented call (events around every launch)
+        ctx.profile(True)
+        ctx.register_batch(items, p2)
+        torch.cuda.synchronize()
         n, ms, u = ctx.profile_read(0)
         groups = {GROUP_NAMES[gid]: round(ctx.profile_read(gid)[1], 3) for gid in range(4)}
         ctx.profile(False)
         terr = max(float(np.linalg.norm(r.pose[:3, 3] - p.T_gt[:3, 3])) for r, p in zip(res, probs))
-        out[name] = {"problems_per_s": round(n_prob / dt, 2), "ms": round(1e3 * dt, 3),
+        out[name] = {"problems_per_s": round(n_prob / dt, 2), "ms": round(1e3 * dt, 3), "lanes": lanes or None,
                      "mean_iterations": float(np.mean([r.iters for r in res])),
                      "statuses": sorted(set(int(r.status) for r in res)),
                      "linearize_GBps": round(72.0 * u / (ms * 1e-3) / 1e9, 2) if ms > 0 else None,

@@ -26,6 +26,7 @@ class Params(C.Structure):
         ("cell_src", C.c_float),
         ("precision", C.c_int32),
         ("flags", C.c_int32),
+        ("lanes", C.c_int32),
     ]
 
 

@@ -6,7 +6,10 @@ hands the query to the overflow pass); only speed does.  Tuned here:
 * the source grid cell, as a factor of the estimated k-NN radius
   (``gicp_estimate_cell``), timed on the fused k-NN covariance;
 * the map grid cell in metres, timed on a two-iteration registration;
-* the number of frames per ``gicp_register_batch`` call.
+* the number of frames per ``gicp_register_batch`` call;
+* the form of a ``gicp_register_batch`` call (batched launches or the work
+  queue) and the lanes per source point of its linearisation;
+* the lanes per source point of ``gicp_track``.
 
 Results are cached as JSON keyed by the device name and a size bucket, in
 ``$GICP_TUNE_CACHE`` (default: ``~/.cache/gicp_tune.json``).
@@ -129,6 +132,63 @@ def tune_batch(ctx, gmap, frames, inits, prm, use_cache=True):
     return best, rec
 
 
+FORMS = (("batched", 0, 2), ("batched", 0, 4), ("queue", 2, 2), ("queue", 2, 4))   # (name, flags, lanes)
+TRACK_LANES = (2, 4)
+
+
+def _with(prm, **kw):
+    import paper_2403_12550_amd as g
+    p = g.Params()
+    for name, _ in g.Params._fields_:
+        setattr(p, name, getattr(prm, name))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def tune_form(ctx, items, prm, use_cache=True, reps=2):
+    """Fastest (flags, lanes) for ``ctx.register_batch(items, prm)`` among
+    FORMS; prm's own form flags and lanes are replaced.  Returns
+    ((flags, lanes), record)."""
+    npts = sum(int(it[0].shape[1]) for it in items)
+    key = _key("form", len(items), npts)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return (cache[key]["flags"], cache[key]["lanes"]), cache[key]
+    times = {}
+    for name, flags, lanes in FORMS:
+        base = prm.flags & ~(1 | 2 | 4)   # keep NO_REUSE, drop the form flags
+        p = _with(prm, flags=base | flags, lanes=lanes)
+        times[(name, flags, lanes)] = _time_ms(lambda: ctx.register_batch(items, p), reps=reps)
+    best = min(times, key=times.get)
+    rec = {"form": best[0], "flags": best[1], "lanes": best[2],
+           "ms": {f"{n}/lanes{ln}": round(t, 4) for (n, _, ln), t in times.items()}}
+    if use_cache:
+        cache[key] = rec
+        _store(cache)
+    return (best[1], best[2]), rec
+
+
+def tune_track_lanes(ctx, frames, gmap, init_pose, motion, prm, use_cache=True, reps=2):
+    """Fastest lanes per source point for ``ctx.track(frames, ...)`` among
+    TRACK_LANES.  Returns (lanes, record)."""
+    npts = sum(int(f.shape[1]) for f in frames)
+    key = _key("track", len(frames), npts)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return cache[key]["lanes"], cache[key]
+    times = {}
+    for lanes in TRACK_LANES:
+        p = _with(prm, lanes=lanes)
+        times[lanes] = _time_ms(lambda: ctx.track(frames, gmap, init_pose, motion, p), reps=reps)
+    best = min(times, key=times.get)
+    rec = {"lanes": best, "ms": {str(k): round(t, 4) for k, t in times.items()}}
+    if use_cache:
+        cache[key] = rec
+        _store(cache)
+    return best, rec
+
+
 def clear_cache():
     try:
         os.remove(CACHE)
@@ -136,4 +196,4 @@ def clear_cache():
         pass
 
 
-__all__ = ["tune_source_cell", "tune_map_cell", "tune_batch", "clear_cache", "CACHE"]
+__all__ = ["tune_source_cell", "tune_map_cell", "tune_batch", "tune_form", "tune_track_lanes", "clear_cache", "CACHE"]

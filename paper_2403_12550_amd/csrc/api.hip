@@ -96,7 +96,7 @@ struct gicp_ctx {
     int32_t* h_progress = nullptr;   // host-mapped progress of the tracking slots: problems done, slots run
     int32_t* d_progress = nullptr;   // its device address
     double slot_work = 0.0;          // slots of the last tracking call that did work
-    int queue_workers[3] = {0, 0, 0};
+    int queue_workers[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // per precision and lanes (2, 4)
     float* h_kth = nullptr;
     int h_kth_cap = 0;   // clouds the pinned estimate buffer holds
     KthJob* h_jobs = nullptr;   // pinned descriptors of the estimate launch
@@ -114,7 +114,7 @@ struct gicp_ctx {
     // graph-captured Gauss-Newton iterations, keyed by batch shape and workspace
     struct GraphEntry {
         int kind;   // 0: batched iterations, 1: one tracked frame
-        int nprob, max_it, acc, motion;
+        int nprob, max_it, acc, motion, lanes;
         int64_t chunks;
         const void *probs, *chunk_prob, *part, *counter;
         hipGraphExec_t exec;
@@ -730,7 +730,18 @@ MapView map_view(const gicp_map* map, const gicp_params* prm) {
 
 bool valid_params(const gicp_params* prm) {
     return prm && prm->max_it >= 0 && prm->r_max > 0.f && prm->precision >= 0 && prm->precision <= 2 &&
+           (prm->lanes == 0 || prm->lanes == 2 || prm->lanes == 4) &&
            (prm->flags & ~(GICP_FLAG_MULTI_LAUNCH | GICP_FLAG_QUEUE | GICP_FLAG_GRAPH | GICP_FLAG_NO_REUSE)) == 0;
+}
+
+// Lanes per source point: the parameter, or the form's default.
+int lanes_of(const gicp_params* prm, int dflt) { return prm->lanes ? prm->lanes : dflt; }
+
+// Work-queue workers that fit on the device at once (asked once per shape).
+int queue_workers(gicp_ctx* c, int acc, int lanes) {
+    int& w = c->queue_workers[acc][lanes == 4 ? 1 : 0];
+    if (!w) w = gn_queue_workers(acc, lanes);
+    return w;
 }
 
 // Graph of the max_it batched iterations for this batch shape and these
@@ -738,11 +749,11 @@ bool valid_params(const gicp_params* prm) {
 constexpr int64_t kGraphBucket = 1024;   // launch grids are padded to a multiple of this many chunks
 constexpr size_t kMaxGraphs = 16;
 
-hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int32_t* chunk_prob,
-                               double* part) {
+hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int lanes,
+                               int32_t* chunk_prob, double* part) {
     for (auto& e : c->graphs)
         if (e.kind == 0 && e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc &&
-            e.probs == c->d_probs && e.chunk_prob == chunk_prob && e.part == part)
+            e.lanes == lanes && e.probs == c->d_probs && e.chunk_prob == chunk_prob && e.part == part)
             return e.exec;
     if (!c->capture_stream) check(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = c->capture_stream;
@@ -750,9 +761,9 @@ hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it,
     check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
     for (int it = 0; it < max_it && err == hipSuccess; ++it) {
-        err = launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, grid, part, acc, true, false, cs);
+        err = launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, grid, part, acc, lanes, true, false, cs);
         if (err == hipSuccess)
-            err = launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, grid, part, acc, false, true, cs);
+            err = launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, grid, part, acc, lanes, false, true, cs);
     }
     const hipError_t end = hipStreamEndCapture(cs, &graph);
     check(err);
@@ -765,17 +776,18 @@ hipGraphExec_t iteration_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it,
         (void)hipGraphExecDestroy(c->graphs.front().exec);
         c->graphs.erase(c->graphs.begin());
     }
-    c->graphs.push_back({0, nprob, max_it, acc, 0, grid, c->d_probs, chunk_prob, part, nullptr, exec});
+    c->graphs.push_back({0, nprob, max_it, acc, 0, lanes, grid, c->d_probs, chunk_prob, part, nullptr, exec});
     return exec;
 }
 
 // Graph of one tracked frame (k_track_begin, then max_it iterations), valid
 // for every frame of a call: which frame runs comes from the device counter.
-hipGraphExec_t track_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int motion, int32_t* counter,
-                           int32_t* chunk_prob, double* part) {
+hipGraphExec_t track_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int acc, int lanes, int motion,
+                           int32_t* counter, int32_t* chunk_prob, double* part) {
     for (auto& e : c->graphs)
         if (e.kind == 1 && e.nprob == nprob && e.chunks == grid && e.max_it == max_it && e.acc == acc &&
-            e.motion == motion && e.probs == c->d_probs && e.chunk_prob == chunk_prob && e.part == part &&
+            e.lanes == lanes && e.motion == motion && e.probs == c->d_probs && e.chunk_prob == chunk_prob &&
+            e.part == part &&
             e.counter == counter)
             return e.exec;
     if (!c->capture_stream) check(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
@@ -784,7 +796,7 @@ hipGraphExec_t track_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int
     check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t err = launch_track_begin(c->d_probs, nprob, counter, chunk_prob, grid, motion, cs);
     for (int it = 0; it < max_it && err == hipSuccess; ++it)
-        err = launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, true, true, cs);
+        err = launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, lanes, true, true, cs);
     const hipError_t end = hipStreamEndCapture(cs, &graph);
     check(err);
     check(end);
@@ -796,7 +808,7 @@ hipGraphExec_t track_graph(gicp_ctx* c, int nprob, int64_t grid, int max_it, int
         (void)hipGraphExecDestroy(c->graphs.front().exec);
         c->graphs.erase(c->graphs.begin());
     }
-    c->graphs.push_back({1, nprob, max_it, acc, motion, grid, c->d_probs, chunk_prob, part, counter, exec});
+    c->graphs.push_back({1, nprob, max_it, acc, motion, lanes, grid, c->d_probs, chunk_prob, part, counter, exec});
     return exec;
 }
 
@@ -1031,11 +1043,11 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
             uint32_t* arrive = ensure<uint32_t>(c->arrive, nprob);
             double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
             const int acc = prm->precision;
-            if (!c->queue_workers[acc]) c->queue_workers[acc] = gn_queue_workers(acc);
-            const int workers = (int)std::min<int64_t>(chunks, c->queue_workers[acc]);
+            const int lanes = lanes_of(prm, kQueueLanes);
+            const int workers = (int)std::min<int64_t>(chunks, queue_workers(c, acc, lanes));
             const int pq = prof_open(c, GICP_PROF_LINEARIZE, 0.0, -2, s);
             check(launch_gn_queue(c->d_probs, nprob, c->d_queue, items, cap, (uint32_t)chunks, arrive, part, workers,
-                                  acc, s));
+                                  acc, lanes, s));
             prof_close(c, pq, s);
         } else if (prm->flags & GICP_FLAG_GRAPH) {
             check(hipMemcpyAsync(c->d_probs, c->h_probs, nprob * sizeof(ProbDev), hipMemcpyHostToDevice, s));
@@ -1044,7 +1056,8 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
             double* part = ensure<double>(c->partials, (size_t)grid * kNumAcc);
             check(launch_chunk_map(c->d_probs, nprob, chunk_prob, s));
             if (grid > chunks) check(launch_fill_i32(chunk_prob + chunks, grid - chunks, -1, s));
-            hipGraphExec_t ge = iteration_graph(c, nprob, grid, prm->max_it, prm->precision, chunk_prob, part);
+            hipGraphExec_t ge =
+                iteration_graph(c, nprob, grid, prm->max_it, prm->precision, lanes_of(prm, kBatchLanes), chunk_prob, part);
             const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, -2, s);
             check(hipGraphLaunch(ge, s));
             prof_close(c, pl, s);
@@ -1057,12 +1070,12 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
                 // units: the work of a launch is only known after the run; the
                 // single-problem case marks its iterations, batches count all
                 const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, it, s);
-                check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision, true,
-                                                false, s));
+                check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision,
+                                                lanes_of(prm, kBatchLanes), true, false, s));
                 prof_close(c, pl, s);
                 const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, it, s);
-                check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision, false,
-                                                true, s));
+                check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision,
+                                                lanes_of(prm, kBatchLanes), false, true, s));
                 prof_close(c, ps, s);
             }
         }
@@ -1179,17 +1192,17 @@ int gicp_register_dev(gicp_ctx* c, const float* src, const float* src_covs, int6
                 uint32_t* arrive = ensure<uint32_t>(c->arrive, 1);
                 double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
                 const int acc = prm->precision;
-                if (!c->queue_workers[acc]) c->queue_workers[acc] = gn_queue_workers(acc);
-                const int workers = (int)std::min<int64_t>(chunks, c->queue_workers[acc]);
+                const int lanes = lanes_of(prm, kQueueLanes);
+                const int workers = (int)std::min<int64_t>(chunks, queue_workers(c, acc, lanes));
                 check(launch_gn_queue(c->dev_probs, 1, c->d_queue, items, cap, (uint32_t)chunks, arrive, part, workers,
-                                      acc, s));
+                                      acc, lanes, s));
             } else {
                 int32_t* chunk_prob = ensure<int32_t>(c->chunk_prob, chunks);
                 double* part = ensure<double>(c->partials, (size_t)chunks * kNumAcc);
                 check(launch_chunk_map(c->dev_probs, 1, chunk_prob, s));
                 for (int it = 0; it < prm->max_it; ++it)
-                    check(launch_gn_iteration_batch(c->dev_probs, 1, chunk_prob, chunks, part, prm->precision, true,
-                                                    true, s));
+                    check(launch_gn_iteration_batch(c->dev_probs, 1, chunk_prob, chunks, part, prm->precision,
+                                                    lanes_of(prm, kBatchLanes), true, true, s));
             }
         }
         check(launch_state_out(c->dev_state, c->d_err, pose, H, b, stats, s));
@@ -1258,6 +1271,7 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
         check(launch_fill_i32(counter, 3, 0, s));
         bool stalled = false;
         const int acc = prm->precision;
+        const int lanes = lanes_of(prm, kTrackLanes);
         if (prm->max_it > 0 && !(prm->flags & (GICP_FLAG_GRAPH | GICP_FLAG_MULTI_LAUNCH))) {
             // iteration slots: (linearise, solve) pairs whose problem the device
             // chooses; the host launches until every problem has finished,
@@ -1293,13 +1307,14 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
                     continue;
                 }
                 const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, (int)launched, s, -5);
-                check(launch_track_slot(c->d_probs, nframes, counter, (int)(launched & 1), grid, part, acc, motion,
-                                        c->d_progress, sync, s));
+                check(launch_track_slot(c->d_probs, nframes, counter, (int)(launched & 1), grid, part, acc, lanes,
+                                        motion, c->d_progress, sync, s));
                 prof_close(c, pl, s);
                 ++launched;
             }
         } else if (prm->max_it > 0 && (prm->flags & GICP_FLAG_GRAPH)) {
-            hipGraphExec_t ge = track_graph(c, nframes, grid, prm->max_it, acc, motion, counter, chunk_prob, part);
+            hipGraphExec_t ge =
+                track_graph(c, nframes, grid, prm->max_it, acc, lanes, motion, counter, chunk_prob, part);
             for (int i = 0; i < nframes; ++i) {
                 const int pm = prof_open(c, GICP_PROF_LINEARIZE, (double)probs[i].n, -2, s, i);
                 check(hipGraphLaunch(ge, s));
@@ -1310,10 +1325,10 @@ int gicp_track(gicp_ctx* c, int nframes, const gicp_frame* frames, const gicp_ma
                 check(launch_track_begin(c->d_probs, nframes, counter, chunk_prob, grid, motion, s));
                 for (int it = 0; it < prm->max_it; ++it) {
                     const int pl = prof_open(c, GICP_PROF_LINEARIZE, (double)probs[i].n, it, s, i);
-                    check(launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, true, false, s));
+                    check(launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, lanes, true, false, s));
                     prof_close(c, pl, s);
                     const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, it, s, i);
-                    check(launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, false, true, s));
+                    check(launch_gn_track_iteration(c->d_probs, chunk_prob, grid, part, acc, lanes, false, true, s));
                     prof_close(c, ps, s);
                 }
             }

@@ -829,8 +829,8 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
 }
 
 // (registers bounded so that five workgroups fit on a CU)
-template <int ACC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_gn_queue(const ProbDev* __restrict__ probs, QueueDev* __restrict__ q,
+template <int ACC, int G>
+__global__ __launch_bounds__(kChunk * G) __attribute__((amdgpu_waves_per_eu(5))) void k_gn_queue(const ProbDev* __restrict__ probs, QueueDev* __restrict__ q,
                                                      uint32_t* __restrict__ items, uint32_t* __restrict__ arrive,
                                                      double* __restrict__ partials) {
     __shared__ uint32_t s_item;
@@ -871,13 +871,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         for (int j = 0; j < 9; ++j) R[j] = uniform(sget<true>(&st->Rf[j]));
 #pragma unroll
         for (int j = 0; j < 3; ++j) t[j] = uniform(sget<true>(&st->tf[j]));
-        chunk_linearize<ACC, kGroup, true, true>(P, c, R, t, partials + ((int64_t)P.part0 + c) * kNumAcc);
+        chunk_linearize<ACC, G, true, true>(P, c, R, t, partials + ((int64_t)P.part0 + c) * kNumAcc);
         if (threadIdx.x == 0) s_last = (atomicAdd(&arrive[p], 1u) == (uint32_t)P.nchunks - 1u) ? 1 : 0;
         __syncthreads();
         if (s_last) {
             handover_acquire();
             // (few loads in flight: this kernel's register budget is the linearisation's)
-            solve_state<kBlock, 4, true>(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
+            solve_state<kChunk * G, 4, true>(partials + (int64_t)P.part0 * kNumAcc, P.nchunks, st);
             if (threadIdx.x == 0) {
                 atomicExch(&arrive[p], 0u);
                 handover_release();   // the new state complete before it is announced
@@ -891,7 +891,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             __syncthreads();
             const uint32_t base = s_base;
             if (base != 0xFFFFFFFFu) {
-                for (int j = threadIdx.x; j < P.nchunks; j += kBlock)
+                for (int j = threadIdx.x; j < P.nchunks; j += kChunk * G)
                     if (base + (uint32_t)j < cap)
                         __hip_atomic_store(&items[base + j], ((p << kChunkBits) | (uint32_t)j) + 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
@@ -1366,34 +1366,66 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-int gn_queue_workers(int acc) {
-    int dev = 0, cus = 0, per = 0;
+namespace {
+
+// Launch tables over the accumulation mode (0..2) and the lanes per point
+// (index 0: two, 1: four).
+constexpr int lanes_index(int lanes) { return lanes == 4 ? 1 : 0; }
+
+template <int ACC, int G>
+void queue_t(unsigned workers, const ProbDev* probs, QueueDev* q, uint32_t* items, uint32_t* arrive,
+             double* partials, hipStream_t s) {
+    hipLaunchKernelGGL((k_gn_queue<ACC, G>), dim3(workers), dim3(kChunk * G), 0, s, probs, q, items, arrive, partials);
+}
+template <int ACC, int G>
+int queue_occupancy() {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<ACC, G>, kChunk * G, 0) != hipSuccess) return 0;
+    return per;
+}
+using QueueFn = void (*)(unsigned, const ProbDev*, QueueDev*, uint32_t*, uint32_t*, double*, hipStream_t);
+using OccFn = int (*)();
+constexpr QueueFn kQueue[3][2] = {{queue_t<0, 2>, queue_t<0, 4>}, {queue_t<1, 2>, queue_t<1, 4>},
+                                  {queue_t<2, 2>, queue_t<2, 4>}};
+constexpr OccFn kQueueOcc[3][2] = {{queue_occupancy<0, 2>, queue_occupancy<0, 4>},
+                                   {queue_occupancy<1, 2>, queue_occupancy<1, 4>},
+                                   {queue_occupancy<2, 2>, queue_occupancy<2, 4>}};
+
+template <int ACC, int G>
+void lin_batch_t(unsigned grid, const ProbDev* probs, const int32_t* chunk_prob, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL((k_gn_linearize_batch<ACC, G>), dim3(grid), dim3(kChunk * G), 0, s, probs, chunk_prob, partials);
+}
+using LinFn = void (*)(unsigned, const ProbDev*, const int32_t*, double*, hipStream_t);
+constexpr LinFn kLinBatch[3][2] = {{lin_batch_t<0, 2>, lin_batch_t<0, 4>}, {lin_batch_t<1, 2>, lin_batch_t<1, 4>},
+                                   {lin_batch_t<2, 2>, lin_batch_t<2, 4>}};
+
+template <int ACC, int G>
+void slot_t(unsigned grid, const ProbDev* probs, int nprob, int32_t* ctl, int parity, double* partials, SlotSync* sy,
+            int motion, int32_t* progress, hipStream_t s) {
+    hipLaunchKernelGGL((k_slot_iterate<ACC, G>), dim3(grid), dim3(kChunk * G), 0, s, probs, nprob, ctl, parity,
+                       partials, sy, motion, progress);
+}
+using SlotFn = void (*)(unsigned, const ProbDev*, int, int32_t*, int, double*, SlotSync*, int, int32_t*, hipStream_t);
+constexpr SlotFn kSlot[3][2] = {{slot_t<0, 2>, slot_t<0, 4>}, {slot_t<1, 2>, slot_t<1, 4>},
+                                {slot_t<2, 2>, slot_t<2, 4>}};
+
+}  // namespace
+
+int gn_queue_workers(int acc, int lanes) {
+    int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-    hipError_t e;
-    switch (acc) {
-        case GICP_ACC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<GICP_ACC_FP32>, kBlock, 0); break;
-        case GICP_ACC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<GICP_ACC_FP64>, kBlock, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gn_queue<GICP_ACC_TWOSUM>, kBlock, 0);
-    }
-    if (e != hipSuccess || per < 1) per = 1;
+    int per = kQueueOcc[acc][lanes_index(lanes)]();
+    if (per < 1) per = 1;
     return cus * per;
 }
 
 hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_t* items, uint32_t cap,
-                           uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, hipStream_t s) {
+                           uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, int lanes,
+                           hipStream_t s) {
     hipLaunchKernelGGL(k_queue_init, dim3(64), dim3(256), 0, s, probs, nprob, q, items, cap, first, arrive);
     hipLaunchKernelGGL(k_queue_post, dim3(nprob), dim3(256), 0, s, probs, nprob, items);
-    switch (acc) {
-        case GICP_ACC_FP32:
-            hipLaunchKernelGGL(k_gn_queue<GICP_ACC_FP32>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
-            break;
-        case GICP_ACC_FP64:
-            hipLaunchKernelGGL(k_gn_queue<GICP_ACC_FP64>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
-            break;
-        default:
-            hipLaunchKernelGGL(k_gn_queue<GICP_ACC_TWOSUM>, dim3(workers), dim3(kBlock), 0, s, probs, q, items, arrive, partials);
-    }
+    kQueue[acc][lanes_index(lanes)]((unsigned)workers, probs, q, items, arrive, partials, s);
     return hipGetLastError();
 }
 
@@ -1403,22 +1435,8 @@ hipError_t launch_chunk_map(const ProbDev* probs, int nprob, int32_t* chunk_prob
 }
 
 hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, int32_t* chunk_prob, int64_t chunks,
-                                     double* partials, int acc, bool linearize, bool solve, hipStream_t s) {
-    if (linearize) {
-        switch (acc) {
-            case GICP_ACC_FP32:
-                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP32>, dim3((unsigned)chunks), dim3(kLinThreads), 0, s,
-                                   probs, chunk_prob, partials);
-                break;
-            case GICP_ACC_FP64:
-                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_FP64>, dim3((unsigned)chunks), dim3(kLinThreads), 0, s,
-                                   probs, chunk_prob, partials);
-                break;
-            default:
-                hipLaunchKernelGGL(k_gn_linearize_batch<GICP_ACC_TWOSUM>, dim3((unsigned)chunks), dim3(kLinThreads), 0,
-                                   s, probs, chunk_prob, partials);
-        }
-    }
+                                     double* partials, int acc, int lanes, bool linearize, bool solve, hipStream_t s) {
+    if (linearize) kLinBatch[acc][lanes_index(lanes)]((unsigned)chunks, probs, chunk_prob, partials, s);
     if (solve)
         hipLaunchKernelGGL(k_gn_solve_batch, dim3(nprob), dim3(kSolveThreads), 0, s, probs, (const double*)partials,
                            chunk_prob);
@@ -1432,23 +1450,8 @@ hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter,
 }
 
 hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, int64_t grid, double* partials, int acc,
-                                     bool linearize, bool solve, hipStream_t s) {
-    constexpr int kT = kChunk * kTrackGroup;
-    if (linearize) {
-        switch (acc) {
-            case GICP_ACC_FP32:
-                hipLaunchKernelGGL((k_gn_linearize_batch<GICP_ACC_FP32, kTrackGroup>), dim3((unsigned)grid), dim3(kT),
-                                   0, s, probs, chunk_prob, partials);
-                break;
-            case GICP_ACC_FP64:
-                hipLaunchKernelGGL((k_gn_linearize_batch<GICP_ACC_FP64, kTrackGroup>), dim3((unsigned)grid), dim3(kT),
-                                   0, s, probs, chunk_prob, partials);
-                break;
-            default:
-                hipLaunchKernelGGL((k_gn_linearize_batch<GICP_ACC_TWOSUM, kTrackGroup>), dim3((unsigned)grid),
-                                   dim3(kT), 0, s, probs, chunk_prob, partials);
-        }
-    }
+                                     int lanes, bool linearize, bool solve, hipStream_t s) {
+    if (linearize) kLinBatch[acc][lanes_index(lanes)]((unsigned)grid, probs, chunk_prob, partials, s);
     if (solve)
         hipLaunchKernelGGL(k_gn_solve_track, dim3(1), dim3(kSolveThreads), 0, s, probs, (const double*)partials,
                            chunk_prob);
@@ -1456,22 +1459,9 @@ hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, 
 }
 
 hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int parity, int64_t grid, double* partials,
-                             int acc, int motion, int32_t* progress, void* sync, hipStream_t s) {
-    constexpr int kT = kChunk * kTrackGroup;
-    SlotSync* sy = (SlotSync*)sync;
-    switch (acc) {
-        case GICP_ACC_FP32:
-            hipLaunchKernelGGL((k_slot_iterate<GICP_ACC_FP32, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s, probs,
-                               nprob, ctl, parity, partials, sy, motion, progress);
-            break;
-        case GICP_ACC_FP64:
-            hipLaunchKernelGGL((k_slot_iterate<GICP_ACC_FP64, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s, probs,
-                               nprob, ctl, parity, partials, sy, motion, progress);
-            break;
-        default:
-            hipLaunchKernelGGL((k_slot_iterate<GICP_ACC_TWOSUM, kTrackGroup>), dim3((unsigned)grid), dim3(kT), 0, s,
-                               probs, nprob, ctl, parity, partials, sy, motion, progress);
-    }
+                             int acc, int lanes, int motion, int32_t* progress, void* sync, hipStream_t s) {
+    kSlot[acc][lanes_index(lanes)]((unsigned)grid, probs, nprob, ctl, parity, partials, (SlotSync*)sync, motion,
+                                   progress, s);
     return hipGetLastError();
 }
 

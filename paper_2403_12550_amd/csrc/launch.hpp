@@ -160,11 +160,16 @@ constexpr int kMaxProblems = 4096;
 
 int gn_blocks(int64_t n);
 hipError_t launch_chunk_map(const ProbDev* probs, int nprob, int32_t* chunk_prob, hipStream_t s);
+// Lanes per source point in the linearisation (gicp_params.lanes 0 picks
+// the form's default; 2 and 4 are built): batched launches, the work queue,
+// sequential tracking.
+constexpr int kBatchLanes = 2, kQueueLanes = 4, kTrackLanes = 4;
 hipError_t launch_gn_iteration_batch(const ProbDev* probs, int nprob, int32_t* chunk_prob, int64_t chunks,
-                                     double* partials, int acc, bool linearize, bool solve, hipStream_t s);
-int gn_queue_workers(int acc);
+                                     double* partials, int acc, int lanes, bool linearize, bool solve, hipStream_t s);
+int gn_queue_workers(int acc, int lanes);
 hipError_t launch_gn_queue(const ProbDev* probs, int nprob, QueueDev* q, uint32_t* items, uint32_t cap,
-                           uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, hipStream_t s);
+                           uint32_t first, uint32_t* arrive, double* partials, int workers, int acc, int lanes,
+                           hipStream_t s);
 hipError_t launch_gn_linearize(const ProbDev& pd, double* partials, int nblocks, int acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gn_solve(const double* partials, int nblocks, RegState* st, hipStream_t s);
@@ -186,10 +191,10 @@ hipError_t launch_track_begin(const ProbDev* probs, int nprob, int32_t* counter,
 // (problems finished, slots run); sync: slot_sync_bytes() of device memory,
 // zero before the first slot (each slot leaves it zero).
 hipError_t launch_track_slot(const ProbDev* probs, int nprob, int32_t* ctl, int parity, int64_t grid, double* partials,
-                             int acc, int motion, int32_t* progress, void* sync, hipStream_t s);
+                             int acc, int lanes, int motion, int32_t* progress, void* sync, hipStream_t s);
 size_t slot_sync_bytes();
 hipError_t launch_gn_track_iteration(const ProbDev* probs, int32_t* chunk_prob, int64_t grid, double* partials, int acc,
-                                     bool linearize, bool solve, hipStream_t s);
+                                     int lanes, bool linearize, bool solve, hipStream_t s);
 
 // Incremental map update (grid.hip): merge the map's sorted run (okeys,
 // opts, ocov; m_old) with new points sorted on their own (nkeys, nvals into

@@ -186,6 +186,54 @@ def test_autotune_choices(g, ctx, tmp_path, monkeypatch):
     gm.close()
 
 
+def test_lanes_per_point_bitwise(g, ctx):
+    """The lanes per source point (gicp_params.lanes) change only how a
+    point's search is split: every form gives bitwise the same registration
+    with 2 and 4 lanes (batched launches, graph replay, work queue,
+    per-registration launches, and gicp_track in its slot, launch-pair and
+    graph forms); other values are refused."""
+    _say("lanes")
+    pr, src, gm = _c1(g, ctx)
+    ref = ctx.register(src, gm, pr.init, g.params(max_it=12))
+    for flags in (0, g.FLAG_GRAPH, g.FLAG_QUEUE, g.FLAG_MULTI_LAUNCH):
+        for lanes in (2, 4):
+            r = ctx.register(src, gm, pr.init, g.params(max_it=12, flags=flags, lanes=lanes))
+            assert (r.pose == ref.pose).all() and (r.H == ref.H).all() and r.iters == ref.iters, (flags, lanes)
+    frames = [src, src, src]
+    tref = ctx.track(frames, gm, pr.init, prm=g.params(max_it=12, conv_rot=1e-6, conv_trans=1e-6))
+    for flags in (0, g.FLAG_MULTI_LAUNCH, g.FLAG_GRAPH):
+        for lanes in (2, 4):
+            tr = ctx.track(frames, gm, pr.init, prm=g.params(max_it=12, conv_rot=1e-6, conv_trans=1e-6,
+                                                             flags=flags, lanes=lanes))
+            for a, b in zip(tref, tr):
+                assert (a.pose == b.pose).all() and (a.H == b.H).all() and a.iters == b.iters, (flags, lanes)
+    for bad in (1, 3, 8, -2):
+        with pytest.raises(g.GicpError):
+            ctx.register(src, gm, pr.init, g.params(max_it=2, lanes=bad))
+    gm.close()
+
+
+def test_autotune_forms(g, ctx, tmp_path, monkeypatch):
+    """The form and lanes tuners time every candidate on real calls, cache
+    their choice, and the chosen form gives the default form's results."""
+    from paper_2403_12550_amd import autotune as at
+    monkeypatch.setattr(at, "CACHE", str(tmp_path / "tune.json"))
+    _say("autotune forms")
+    pr, src, gm = _c1(g, ctx, n=5000)
+    items = [(src, None, gm, pr.init)] * 4
+    prm = g.params(max_it=10)
+    (flags, lanes), rec = at.tune_form(ctx, items, prm)
+    assert (rec["form"], flags, lanes) in [(n, f, ln) for n, f, ln in at.FORMS] and len(rec["ms"]) == len(at.FORMS)
+    assert at.tune_form(ctx, items, prm)[1] == rec   # cached
+    ref = ctx.register_batch(items, prm)
+    got = ctx.register_batch(items, g.params(max_it=10, flags=flags, lanes=lanes))
+    for a, b in zip(ref, got):
+        assert (a.pose == b.pose).all()
+    lanes_t, rect = at.tune_track_lanes(ctx, [src, src], gm, pr.init, 0, prm)
+    assert lanes_t in at.TRACK_LANES and len(rect["ms"]) == len(at.TRACK_LANES)
+    gm.close()
+
+
 def test_batch_more_than_one_segment_group(g, ctx):
     """More sources than one segmented grid holds (255): the call splits them
     into groups; every result equals the single registration."""
