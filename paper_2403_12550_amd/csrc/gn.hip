@@ -587,14 +587,17 @@ __device__ __forceinline__ int pre_word(int t) {
                              : (t == 17 ? (int)(offsetof(RegState, conv_trans) / 8) : (int)(offsetof(RegState, iters) / 8)));
 }
 
+// The results of one update, in LDS: the new pose itself is left in the
+// workspace (H[0..16)) when `moved`.
+struct SolveOut {
+    int32_t iters, status, done, converged, moved;
+};
+
 // Thread-0 part of the solve: v holds the 29 reduced sums, pre the words
-// above; H and L live in LDS (workspace of 72 doubles).  Inlined where the
-// kernel bounds its registers (the iteration slots); called through
-// solve_update elsewhere, so that the single-thread FP64 code does not raise
-// the register footprint of the kernels that embed it.
-template <bool DEV = false>
-__device__ __forceinline__ void solve_update_inl(const double* v, const double* pre, RegState* st, double* H,
-                                                 double* L) {
+// above; H and L live in LDS (workspace of 72 doubles).  Computes only: the
+// results go to `o` and H[0..16), and solve_publish stores them.
+__device__ __forceinline__ void solve_update_inl(const double* v, const double* pre, double* H, double* L,
+                                                 SolveOut* o) {
     int32_t im[2];
     __builtin_memcpy(im, &pre[18], 8);
     const int32_t iters = im[0] + 1;
@@ -607,14 +610,14 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
             H[6 * j + i] = v[q];
             ++q;
         }
-    for (int j = 0; j < 21; ++j) sput<DEV>(&st->H[j], v[j]);
-    for (int j = 0; j < 6; ++j) sput<DEV>(&st->b[j], v[21 + j]);
-    sput<DEV>(&st->cost, v[27]);
-    sput<DEV>(&st->n_inl, v[28]);
-    sput<DEV>(&st->iters, iters);
+    o->iters = iters;
+    o->status = 0;
+    o->done = 0;
+    o->converged = 0;
+    o->moved = 0;
     if (v[28] < 6.0) {
-        sput<DEV>(&st->status, (int32_t)GICP_E_NO_CORR);
-        sput<DEV>(&st->done, 1);
+        o->status = GICP_E_NO_CORR;
+        o->done = 1;
         return;
     }
     // Cholesky H = L L^T; a pivot not above 1e-12 * max(diag H) fails.  The
@@ -634,8 +637,8 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= Lr[6 * j + k] * Lr[6 * j + k];
         if (!(s > floor_) || !isfinite(s)) {
-            sput<DEV>(&st->status, (int32_t)GICP_E_DEGENERATE);
-            sput<DEV>(&st->done, 1);
+            o->status = GICP_E_DEGENERATE;
+            o->done = 1;
             return;
         }
         Lr[7 * j] = sqrt(s);
@@ -679,29 +682,55 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
             for (int k = 0; k < 4; ++k) s += E[4 * i + k] * P[4 * k + j];
             T[4 * i + j] = s;
         }
-    for (int i = 0; i < 16; ++i) sput<DEV>(&st->pose[i], T[i]);
+    o->moved = 1;
     const double nw = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
     const double nv = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
     if (nw < conv_rot && nv < conv_trans) {
-        sput<DEV>(&st->converged, 1);
-        sput<DEV>(&st->done, 1);
+        o->converged = 1;
+        o->done = 1;
     } else if (iters >= max_it) {
-        sput<DEV>(&st->done, 1);
-    }
-    for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 3; ++j) sput<DEV>(&st->Rf[3 * i + j], (float)T[4 * i + j]);
-        sput<DEV>(&st->tf[i], (float)T[4 * i + 3]);
+        o->done = 1;
     }
 }
 
-// The update with device-coherent stores (read by other workgroups of a
-// persistent launch).
-__device__ __noinline__ void solve_update_dev(const double* v, const double* pre, RegState* st, double* H, double* L) {
-    solve_update_inl<true>(v, pre, st, H, L);
+// The update's stores, spread over the workgroup's threads (called by every
+// thread; at least 64): the new pose (and its FP32 copy) when it moved; when
+// the registration ends, the last linearisation's H, b, cost and inliers
+// (the values a caller reads, written once); iterations and flags.
+template <bool DEV>
+__device__ __forceinline__ void solve_publish(const SolveOut& o, const double* T, const double* v, RegState* st,
+                                              int t) {
+    if (o.moved) {
+        if (t < 16) {
+            sput<DEV>(&st->pose[t], T[t]);
+        } else if (t < 25) {
+            const int k = t - 16;
+            sput<DEV>(&st->Rf[k], (float)T[4 * (k / 3) + k % 3]);
+        } else if (t < 28) {
+            const int k = t - 25;
+            sput<DEV>(&st->tf[k], (float)T[4 * k + 3]);
+        }
+    }
+    if (o.done && t >= 32 && t < 32 + kNumAcc) {
+        const int j = t - 32;
+        if (j < 21) sput<DEV>(&st->H[j], v[j]);
+        else if (j < 27) sput<DEV>(&st->b[j - 21], v[j]);
+        else if (j == 27) sput<DEV>(&st->cost, v[27]);
+        else sput<DEV>(&st->n_inl, v[28]);
+    }
+    if (t == 63) {
+        sput<DEV>(&st->iters, o.iters);
+        if (o.status) sput<DEV>(&st->status, o.status);
+        if (o.converged) sput<DEV>(&st->converged, 1);
+        if (o.done) sput<DEV>(&st->done, 1);
+    }
+    if (DEV) handover_release();
 }
 
-__device__ __noinline__ void solve_update(const double* v, const double* pre, RegState* st, double* H, double* L) {
-    solve_update_inl(v, pre, st, H, L);
+// The update as a call, for the work queue: its registers then do not add
+// to the queue kernel's.
+__device__ __noinline__ void solve_update_call(const double* v, const double* pre, double* H, double* L, SolveOut* o) {
+    solve_update_inl(v, pre, H, L, o);
 }
 
 namespace {
@@ -727,7 +756,7 @@ constexpr int kSolveParts = 32;
 template <int NT, int KU, bool DEV = false>
 __device__ __forceinline__ void solve_state(const double* __restrict__ partials, int nparts,
                                             RegState* __restrict__ st) {
-    static_assert(NT >= kPreFields && NT >= kNumAcc, "solve block size");
+    static_assert(NT >= kPreFields && NT >= kNumAcc && NT >= 64, "solve block size");
     __shared__ double s_part[kNumAcc][kSolveParts];
     __shared__ double s_v[kNumAcc];
     __shared__ double s_pre[kPreFields];
@@ -786,10 +815,13 @@ __device__ __forceinline__ void solve_state(const double* __restrict__ partials,
         }
     }
     __syncthreads();
+    __shared__ SolveOut s_out;
     if (t == 0) {
-        if (DEV) solve_update_dev(s_v, s_pre, st, s_HL, s_HL + 36);
-        else solve_update(s_v, s_pre, st, s_HL, s_HL + 36);
+        if (DEV) solve_update_call(s_v, s_pre, s_HL, s_HL + 36, &s_out);
+        else solve_update_inl(s_v, s_pre, s_HL, s_HL + 36, &s_out);
     }
+    __syncthreads();
+    solve_publish<DEV>(s_out, s_HL, s_v, st, t);
     __syncthreads();
 }
 
@@ -1113,7 +1145,7 @@ __global__ __launch_bounds__(kChunk * G) __attribute__((amdgpu_waves_per_eu(5)))
     const ProbDev* __restrict__ probs, int nprob, int32_t* __restrict__ ctl, int parity, double* __restrict__ partials,
     SlotSync* __restrict__ sync, int motion, int32_t* __restrict__ progress) {
     constexpr int NT = kChunk * G;
-    static_assert(NT >= kNumAcc && NT >= kPreFields && NT > kSolveParts, "slot block size");
+    static_assert(NT >= kNumAcc && NT >= kPreFields && NT > kSolveParts && NT >= 64, "slot block size");
     static_assert(kGroupRows >= kSolveParts, "the group rows also hold the groups' sums");
     __shared__ int s_last;
     __shared__ double s_rows[kGroupRows][kNumAcc];
@@ -1177,7 +1209,10 @@ __global__ __launch_bounds__(kChunk * G) __attribute__((amdgpu_waves_per_eu(5)))
             if (t < kSolveParts) __hip_atomic_store(&sync->group[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t == kSolveParts) __hip_atomic_store(&sync->groups, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
-            if (t == 0) solve_update_inl(s_v, s_pre, st, s_HL, s_HL + 36);
+            __shared__ SolveOut s_out;
+            if (t == 0) solve_update_inl(s_v, s_pre, s_HL, s_HL + 36, &s_out);
+            __syncthreads();
+            solve_publish<false>(s_out, s_HL, s_v, st, t);
             __syncthreads();
             solver = true;
         }
