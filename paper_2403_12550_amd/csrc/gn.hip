@@ -348,70 +348,62 @@ __device__ __forceinline__ void store4_dev(float4* p, float4 v) {
     __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Linearisation of source point i at the pose (R, t), evaluated by a group of
-// G lanes (lane l of the group): on return, v[0..29) holds the point's
-// 21 unique terms of J^T M J, the 6 of J^T M d, d^T M d and 1 (the inlier
-// count); the return value is false (and v untouched) when the point has no
-// correspondence within r_max or a singular combined covariance.
-// Point i of the problem's processing order: the grid-cell order when the
-// problem carries its sorted source (ssrc, sscov), else the caller's order.
-template <int G, bool COH = false>
-__device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, const float* R, const float* t,
-                                                float* v, int l) {
-    const int64_t n = P.n;
+// The linearisation of one source point, in three parts that chunk_linearize
+// runs on different lanes: the query point q = R x + t; the correspondence
+// (kept from the previous iteration, or searched by a group of G lanes); and
+// the terms.  On success point_terms leaves in v[0..29) the point's 21 unique
+// terms of J^T M J, the 6 of J^T M d, d^T M d and 1 (the inlier count); it
+// returns false (v untouched) when the point has no correspondence within
+// r_max or a singular combined covariance.  Point i of the problem's
+// processing order: the grid-cell order when the problem carries its sorted
+// source (ssrc, sscov), else the caller's order.
+__device__ __forceinline__ void point_query(const ProbDev& P, int64_t i, const float* R, const float* t, float& qx,
+                                            float& qy, float& qz) {
     float x, y, z;
-    const float* cv;
     if (P.ssrc) {
         const float4 p4 = gload(P.ssrc, i);
         x = p4.x;
         y = p4.y;
         z = p4.z;
-        cv = P.sscov;
     } else {
         x = gload(P.src, i);
-        y = gload(P.src, n + i);
-        z = gload(P.src, 2 * n + i);
-        cv = P.scov;
+        y = gload(P.src, P.n + i);
+        z = gload(P.src, 2 * P.n + i);
     }
-    const float qx = R[0] * x + R[1] * y + R[2] * z + t[0];
-    const float qy = R[3] * x + R[4] * y + R[5] * z + t[1];
-    const float qz = R[6] * x + R[7] * y + R[8] * z + t[2];
-    const MapView& map = P.map;
-    // the previous iteration's match stands while q stays within the radius
-    // its search certified (the nearest mean cannot have changed); otherwise
-    // search again, starting from that match (unless every search is to
-    // start afresh)
-    const int32_t hint = P.fresh ? -1 : (COH ? sget<true>(P.nn_prev + i) : gload((const int32_t*)P.nn_prev, i));
-    bool reuse = false;
-    if (hint >= 0) {
-        const float4 cq = COH ? load4_dev(P.nn_cache + i) : gload((const float4*)P.nn_cache, i);
-        const float ex = qx - cq.x, ey = qy - cq.y, ez = qz - cq.z;
-        reuse = sqrtf(ex * ex + ey * ey + ez * ez) < cq.w;
-    }
-    int32_t pos;
-    if (reuse) {
-        const float4 p = gload(map.g.spts, hint);
-        pos = rank_key(qx, qy, qz, p.x, p.y, p.z) <= map.r_max2 ? hint : -1;
-    } else {
-        float free_r;
-        pos = nearest<true, G>(map, qx, qy, qz, l, hint, &free_r);
-        if (l == 0) {
-            if (COH) {
-                sput<true>(P.nn_prev + i, pos);
-                store4_dev(P.nn_cache + i, make_float4(qx, qy, qz, free_r));
-            } else {
-                gstore(P.nn_prev, i, pos);
-                gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
-            }
-        }
-    }
+    qx = R[0] * x + R[1] * y + R[2] * z + t[0];
+    qy = R[3] * x + R[4] * y + R[5] * z + t[1];
+    qz = R[6] * x + R[7] * y + R[8] * z + t[2];
+}
+
+// The previous iteration's match of point i stands while q stays within the
+// radius its search certified (the nearest mean cannot have changed): the
+// match (reuse), or the search's starting candidate (hint, -1 for none).
+template <bool COH>
+__device__ __forceinline__ bool point_reuse(const ProbDev& P, int64_t i, float qx, float qy, float qz,
+                                            int32_t& hint) {
+    hint = P.fresh ? -1 : (COH ? sget<true>(P.nn_prev + i) : gload((const int32_t*)P.nn_prev, i));
+    if (hint < 0) return false;
+    const float4 cq = COH ? load4_dev(P.nn_cache + i) : gload((const float4*)P.nn_cache, i);
+    const float ex = qx - cq.x, ey = qy - cq.y, ez = qz - cq.z;
+    return sqrtf(ex * ex + ey * ey + ez * ez) < cq.w;
+}
+
+// The terms of point i (query q at the pose R) against the map Gaussian at
+// sorted position pos; the gate is tested here (a kept match may have left
+// it; a searched one passes by construction).
+__device__ __forceinline__ bool point_terms(const ProbDev& P, int64_t i, const float* R, float qx, float qy,
+                                            float qz, int32_t pos, float* v) {
     if (pos < 0) return false;
+    const int64_t n = P.n;
+    const float* cv = P.ssrc ? P.sscov : P.scov;
+    const MapView& map = P.map;
     const float4 mu = gload(map.g.spts, pos);
     const float4 ca = gload(map.scov, 2 * (int64_t)pos);
     const float4 cb = gload(map.scov, 2 * (int64_t)pos + 1);
-    // source covariance rotated: A = R Cs, S = A R^T
     const float c00 = gload(cv, i), c01 = gload(cv, n + i), c02 = gload(cv, 2 * n + i);
     const float c11 = gload(cv, 3 * n + i), c12 = gload(cv, 4 * n + i), c22 = gload(cv, 5 * n + i);
+    if (!(rank_key(qx, qy, qz, mu.x, mu.y, mu.z) <= map.r_max2)) return false;
+    // source covariance rotated: A = R Cs, S = A R^T
     const float a00 = R[0] * c00 + R[1] * c01 + R[2] * c02;
     const float a01 = R[0] * c01 + R[1] * c11 + R[2] * c12;
     const float a02 = R[0] * c02 + R[1] * c12 + R[2] * c22;
@@ -476,24 +468,87 @@ __device__ __forceinline__ bool linearize_point(const ProbDev& P, int64_t i, con
 }
 
 
-// One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, G
-// lanes per point.  The group's first lane stores the point's 29 values in an
-// LDS row (zeros when it is not an inlier); threads 0..28 then sum one column
-// each over the 64 rows in a fixed order, and write the chunk's FP64 partial
+// One work item: the kChunk points [c*kChunk, (c+1)*kChunk) of a cloud, in
+// a workgroup of kChunk x G threads.  One lane per point finds q and whether
+// its match stands; the points that must search are packed, G lanes each,
+// into the first groups (a wavefront whose points all keep their matches
+// then runs no search code); one lane per point computes the terms into the
+// point's LDS row (zeros when it is not an inlier), so the per-point
+// arithmetic runs once per point, not once per lane; threads 0..28 then sum
+// one column each over the 64 rows in a fixed order, and write the chunk's FP64 partial
 // (with DEV device-coherently, completed before the closing barrier, for a
 // hand-over within the launch; with COH also the points' reuse state, for
 // a launch in which another workgroup may take the chunk's next iteration).
 template <int ACC, int G = kGroup, bool DEV = false, bool COH = false>
 __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, const float* R, const float* t,
                                                 double* __restrict__ out) {
+    static_assert(kChunk == 64, "one wavefront holds a work item's points");
     __shared__ float s_val[kChunk][kNumAcc + 1];
-    const int l = threadIdx.x & (G - 1);
-    const int pt = threadIdx.x / G;
-    const int64_t i = c * kChunk + pt;
-    float v[kNumAcc];
-    bool ok = false;
-    if (i < P.n) ok = linearize_point<G, COH>(P, i, R, t, v, l);
-    if (l == 0) {
+    __shared__ float s_q[kChunk][3];
+    __shared__ int32_t s_pos[kChunk];
+    __shared__ int32_t s_hint[kChunk];
+    __shared__ int32_t s_list[kChunk];
+    __shared__ int32_t s_nsearch;
+    const int tid = threadIdx.x;
+    // 1. one lane per point (the first wavefront): q, and whether the
+    //    previous match stands; the points that must search are listed in
+    //    point order
+    if (tid < kChunk) {
+        const int pt = tid;
+        const int64_t i = c * kChunk + pt;
+        int32_t pos = -1;
+        bool need = false;
+        if (i < P.n) {
+            float qx, qy, qz;
+            point_query(P, i, R, t, qx, qy, qz);
+            s_q[pt][0] = qx;
+            s_q[pt][1] = qy;
+            s_q[pt][2] = qz;
+            int32_t hint;
+            if (point_reuse<COH>(P, i, qx, qy, qz, hint)) {
+                pos = hint;
+            } else {
+                need = true;
+                s_hint[pt] = hint;
+            }
+        }
+        s_pos[pt] = pos;
+        const uint64_t m = __ballot(need);
+        if (need) s_list[__popcll(m & ((1ull << pt) - 1ull))] = pt;
+        if (pt == 0) s_nsearch = (int32_t)__popcll(m);
+    }
+    __syncthreads();
+    // 2. G lanes per listed point: the searches, packed into the first
+    //    groups, so that only the wavefronts holding them run search code
+    {
+        const int grp = tid / G, l = tid & (G - 1);
+        if (grp < s_nsearch) {
+            const int pt = s_list[grp];
+            const int64_t i = c * kChunk + pt;
+            const float qx = s_q[pt][0], qy = s_q[pt][1], qz = s_q[pt][2];
+            float free_r;
+            const int32_t pos = nearest<true, G>(P.map, qx, qy, qz, l, s_hint[pt], &free_r);
+            if (l == 0) {
+                if (COH) {
+                    sput<true>(P.nn_prev + i, pos);
+                    store4_dev(P.nn_cache + i, make_float4(qx, qy, qz, free_r));
+                } else {
+                    gstore(P.nn_prev, i, pos);
+                    gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
+                }
+                s_pos[pt] = pos;
+            }
+        }
+    }
+    __syncthreads();
+    // 3. one lane per point: the terms, stored as the point's LDS row (zeros
+    //    when it is not an inlier)
+    if (tid < kChunk) {
+        const int pt = tid;
+        const int64_t i = c * kChunk + pt;
+        float v[kNumAcc];
+        bool ok = false;
+        if (i < P.n) ok = point_terms(P, i, R, s_q[pt][0], s_q[pt][1], s_q[pt][2], s_pos[pt], v);
 #pragma unroll
         for (int j = 0; j < kNumAcc; ++j) s_val[pt][j] = ok ? v[j] : 0.f;
     }
