@@ -479,6 +479,32 @@ __device__ __forceinline__ bool point_terms(const ProbDev& P, int64_t i, const f
 // (with DEV device-coherently, completed before the closing barrier, for a
 // hand-over within the launch; with COH also the points' reuse state, for
 // a launch in which another workgroup may take the chunk's next iteration).
+// The listed points' searches, GS lanes each (groups of GS consecutive
+// threads; the groups beyond the list idle): each stores its point's match
+// and certified radius (the reuse state) and the match in s_pos.
+template <int GS, bool COH>
+__device__ __forceinline__ void search_listed(const ProbDev& P, int64_t c, int ns, const int32_t* s_list,
+                                              const int32_t* s_hint, const float (*s_q)[3], int32_t* s_pos) {
+    const int tid = threadIdx.x;
+    const int grp = tid / GS, l = tid & (GS - 1);
+    if (grp >= ns) return;
+    const int pt = s_list[grp];
+    const int64_t i = c * kChunk + pt;
+    const float qx = s_q[pt][0], qy = s_q[pt][1], qz = s_q[pt][2];
+    float free_r;
+    const int32_t pos = nearest<true, GS>(P.map, qx, qy, qz, l, s_hint[pt], &free_r);
+    if (l == 0) {
+        if (COH) {
+            sput<true>(P.nn_prev + i, pos);
+            store4_dev(P.nn_cache + i, make_float4(qx, qy, qz, free_r));
+        } else {
+            gstore(P.nn_prev, i, pos);
+            gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
+        }
+        s_pos[pt] = pos;
+    }
+}
+
 template <int ACC, int G = kGroup, bool DEV = false, bool COH = false>
 __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, const float* R, const float* t,
                                                 double* __restrict__ out) {
@@ -518,26 +544,22 @@ __device__ __forceinline__ void chunk_linearize(const ProbDev& P, int64_t c, con
         if (pt == 0) s_nsearch = (int32_t)__popcll(m);
     }
     __syncthreads();
-    // 2. G lanes per listed point: the searches, packed into the first
-    //    groups, so that only the wavefronts holding them run search code
+    // 2. the searches, packed into the first groups, so that only the
+    //    wavefronts holding them run search code; when few points search,
+    //    each gets more lanes (a work item lasts as long as its slowest
+    //    search: in iterations where most matches stand, the few searching
+    //    points are the critical path)
     {
-        const int grp = tid / G, l = tid & (G - 1);
-        if (grp < s_nsearch) {
-            const int pt = s_list[grp];
-            const int64_t i = c * kChunk + pt;
-            const float qx = s_q[pt][0], qy = s_q[pt][1], qz = s_q[pt][2];
-            float free_r;
-            const int32_t pos = nearest<true, G>(P.map, qx, qy, qz, l, s_hint[pt], &free_r);
-            if (l == 0) {
-                if (COH) {
-                    sput<true>(P.nn_prev + i, pos);
-                    store4_dev(P.nn_cache + i, make_float4(qx, qy, qz, free_r));
-                } else {
-                    gstore(P.nn_prev, i, pos);
-                    gstore(P.nn_cache, i, make_float4(qx, qy, qz, free_r));
-                }
-                s_pos[pt] = pos;
-            }
+        // (four-lane launches only: they are latency-bound; the two-lane
+        // ones are issue-bound, and the wider searches' registers would cost
+        // them occupancy, as they would the work queue)
+        constexpr int NT = kChunk * G;
+        constexpr bool kWiden = G == 4 && !COH;
+        const int ns = s_nsearch;
+        if (ns > 0) {
+            if (kWiden && ns * 16 <= NT) search_listed<kWiden ? 16 : G, COH>(P, c, ns, s_list, s_hint, s_q, s_pos);
+            else if (kWiden && ns * 8 <= NT) search_listed<kWiden ? 8 : G, COH>(P, c, ns, s_list, s_hint, s_q, s_pos);
+            else search_listed<G, COH>(P, c, ns, s_list, s_hint, s_q, s_pos);
         }
     }
     __syncthreads();
