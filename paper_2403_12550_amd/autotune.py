@@ -23,7 +23,7 @@ import os
 CACHE = os.environ.get("GICP_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "gicp_tune.json"))
 
 SRC_FACTORS = (0.6, 0.75, 0.9, 1.0, 1.2, 1.5)
-MAP_CELLS = (0.015, 0.02, 0.025, 0.03, 0.04, 0.05)
+MAP_CELLS = (0.02, 0.03, 0.04, 0.045, 0.05, 0.055, 0.06)
 BATCHES = (1, 4, 8, 16, 32)
 
 
