@@ -224,8 +224,8 @@ int gicp_map_info(const gicp_map* map, int64_t* m, float* cell);
 /* Nearest map mean of each query within r_max: the correspondence search of
  * the registration (Sec. 3: correspondences come from nearest-neighbour
  * search; Eq. MLE_for_T pairs each source point with one map Gaussian), run
- * by the same device code the batched Gauss-Newton iterations use, exposed so
- * that it can be checked and used on its own.
+ * by the same device code the Gauss-Newton iterations use, exposed so that
+ * it can be checked and used on its own.
  *   queries  SoA [3][nq] (device), points already in the map frame (q = R x + t)
  *   r_max    gate in metres: a mean is accepted when its key <= fl(r_max * r_max)
  *   hints    nullable int32 [nq] (device): a map index per query tried as the
@@ -243,9 +243,16 @@ int gicp_map_info(const gicp_map* map, int64_t* m, float* cell);
  *            match, margins for FP32 rounding included -- the bound under
  *            which the registration keeps a match between iterations;
  *            -1 when there is no match or no margin
- * Asynchronous.  GICP_E_ARG for null pointers, nq < 0 or r_max <= 0. */
+ *   lanes    lanes per query splitting its search: 0 or 2 (as in two-lane
+ *            launches), 4, 8 or 16 (as in four-lane launches such as the
+ *            tracking ones, whose searches of few points take 8 or 16 lanes);
+ *            the matches and keys are the same, the radius may differ (each a
+ *            valid bound)
+ * Asynchronous.  GICP_E_ARG for null pointers, nq < 0, r_max <= 0 or lanes
+ * outside {0, 2, 4, 8, 16}. */
 int gicp_map_nearest(gicp_ctx* ctx, gicp_map* map, const float* queries, int64_t nq, float r_max,
-                     const int32_t* hints, int32_t* idx, float* d2, float* radius, void* stream);
+                     const int32_t* hints, int32_t* idx, float* d2, float* radius, int32_t lanes,
+                     void* stream);
 
 /* Registers a source cloud against a map by Gauss-Newton on Eq. MLE_for_T.
  *   src        SoA [3][n] source points (device)

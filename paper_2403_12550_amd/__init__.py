@@ -210,9 +210,12 @@ class Context:
         lib().gicp_map_info(h, C.byref(m), C.byref(c))
         return Map(h, int(m.value), float(c.value))
 
-    def map_nearest(self, gmap: Map, queries, r_max: float, hints=None, want_radius: bool = False):
+    def map_nearest(self, gmap: Map, queries, r_max: float, hints=None, want_radius: bool = False,
+                    lanes: int = 0):
         """Nearest map mean of each query [3, nq] (map frame) within r_max by the
-        registration's own search: (idx int32 [nq], d2 float32 [nq], radius or None)."""
+        registration's own search (lanes per query: 0 or 2 as two-lane
+        launches, 4, 8 or 16 as four-lane ones such as tracking): (idx int32 [nq],
+        d2 float32 [nq], radius or None)."""
         import torch
         _check_f32_cuda(queries, 3, "queries")
         nq = queries.shape[1]
@@ -223,7 +226,7 @@ class Context:
         d2 = torch.empty(nq, dtype=torch.float32, device=queries.device)
         rad = torch.empty(nq, dtype=torch.float32, device=queries.device) if want_radius else None
         st = lib().gicp_map_nearest(self.handle, gmap.handle, _ptr(queries), nq, r_max, _ptr(hints), _ptr(idx),
-                                    _ptr(d2), _ptr(rad), _stream())
+                                    _ptr(d2), _ptr(rad), int(lanes), _stream())
         if st != GICP_OK:
             raise GicpError(st, "gicp_map_nearest")
         return idx, d2, rad

@@ -102,7 +102,7 @@ SIGNATURES = {
     "gicp_map_build": (C.c_int, [P, P, P, I64, C.c_float, C.c_int, C.c_float, C.POINTER(P), P]),
     "gicp_map_destroy": (C.c_int, [P]),
     "gicp_map_info": (C.c_int, [P, C.POINTER(I64), C.POINTER(C.c_float)]),
-    "gicp_map_nearest": (C.c_int, [P, P, P, I64, C.c_float, P, P, P, P, P]),
+    "gicp_map_nearest": (C.c_int, [P, P, P, I64, C.c_float, P, P, P, P, C.c_int32, P]),
     "gicp_register": (C.c_int, [P, P, P, I64, P, D16, C.POINTER(Params), D16, D36, D6, P,
                                 C.POINTER(Stats), P]),
     "gicp_register_dev": (C.c_int, [P, P, P, I64, P, P, C.POINTER(Params), P, P, P, P, P, P]),

@@ -1373,8 +1373,9 @@ int gicp_register_pair(gicp_ctx* c, const float* src, const float* src_covs, int
 }
 
 int gicp_map_nearest(gicp_ctx* c, gicp_map* mp, const float* queries, int64_t nq, float r_max,
-                     const int32_t* hints, int32_t* idx, float* d2, float* radius, void* stream) {
+                     const int32_t* hints, int32_t* idx, float* d2, float* radius, int32_t lanes, void* stream) {
     if (!c || !mp || nq < 0 || !(r_max > 0.f) || !std::isfinite(r_max) || nq >= (1ll << 31)) return GICP_E_ARG;
+    if (lanes != 0 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16) return GICP_E_ARG;
     if (nq > 0 && (!queries || !idx || !d2)) return GICP_E_ARG;
     try {
         check(hipSetDevice(c->device));
@@ -1391,7 +1392,7 @@ int gicp_map_nearest(gicp_ctx* c, gicp_map* mp, const float* queries, int64_t nq
         gicp_params prm;
         gicp_params_default(&prm);
         prm.r_max = r_max;
-        check(launch_map_nearest(map_view(mp, &prm), queries, nq, hints, inv, idx, d2, radius, s));
+        check(launch_map_nearest(map_view(mp, &prm), queries, nq, hints, inv, idx, d2, radius, lanes ? lanes : 2, s));
         return GICP_OK;
     } catch (const HipError& e) {
         return status_of(e);

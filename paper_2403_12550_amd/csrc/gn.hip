@@ -14,6 +14,7 @@
 #include <float.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -193,14 +194,16 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
         // the cell's candidates are loaded kB at a time before any is
         // ranked, so that a lane waits once per batch rather than once per
         // candidate (slots past the cell reload its first point and are not
-        // ranked); the (key, index) minimum does not depend on the order
+        // ranked; a last batch of at most kB / 2 candidates loads kB / 2
+        // slots); the (key, index) minimum does not depend on the order
         constexpr int kB = scan_batch<G>();
-        for (uint32_t j0 = 0; j0 < cnt; j0 += kB) {
-            float4 pb[kB];
+        auto batch = [&](uint32_t j0, auto width) __attribute__((always_inline)) {
+            constexpr int W = decltype(width)::value;
+            float4 pb[W];
 #pragma unroll
-            for (int u = 0; u < kB; ++u) pb[u] = gload(g.spts, (int64_t)start + (j0 + u < cnt ? j0 + u : 0));
+            for (int u = 0; u < W; ++u) pb[u] = gload(g.spts, (int64_t)start + (j0 + u < cnt ? j0 + u : 0));
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
+            for (int u = 0; u < W; ++u) {
                 if (j0 + u < cnt) {
                     const int32_t pj = (int32_t)(start + j0 + u);
                     const float4 p = pb[u];
@@ -209,7 +212,10 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
                     take<TRACK2>(v, pj, best, pos, sec);
                 }
             }
-        }
+        };
+        uint32_t j0 = 0;
+        for (; j0 + kB / 2 < cnt; j0 += kB) batch(j0, std::integral_constant<int, kB>());
+        if (kB > 1 && j0 < cnt) batch(j0, std::integral_constant<int, (kB > 1 ? kB / 2 : 1)>());
     };
     if (fin) {
         for (int j = l; j < 27; j += G) {
@@ -1383,14 +1389,16 @@ __global__ __launch_bounds__(kBlock) void k_overlap(MapView m, const float* __re
 }
 
 // Nearest map mean of arbitrary queries by the linearisation's own search
-// (nearest<true, kLinGroup>), with its certified radius: the match, its FP32
+// (nearest<true, G>: G = 2 as the two-lane launches, 4, 8 or 16 as the
+// four-lane ones, whose searches of few points take 8 or 16 lanes), with its
+// certified radius: the match, its FP32
 // key and the radius (the query can move by less than it without changing
 // its nearest mean), or -1 / +inf / -1 when no mean lies within the gate.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_map_nearest(MapView m, const float* __restrict__ q, int64_t nq,
                                                        const int32_t* __restrict__ hints,
                                                        const int32_t* __restrict__ inv, int32_t* __restrict__ idx,
                                                        float* __restrict__ d2, float* __restrict__ radius) {
-    constexpr int G = kLinGroup;
     const int l = threadIdx.x & (G - 1);
     const int64_t i = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
     if (i >= nq) return;   // uniform over each lane group
@@ -1605,11 +1613,17 @@ hipError_t launch_overlap(const MapView& m, const float* src, int64_t n, const P
 }
 
 hipError_t launch_map_nearest(const MapView& m, const float* q, int64_t nq, const int32_t* hints, const int32_t* inv,
-                              int32_t* idx, float* d2, float* radius, hipStream_t s) {
+                              int32_t* idx, float* d2, float* radius, int lanes, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
-    const int per = kBlock / kLinGroup;
-    hipLaunchKernelGGL(k_map_nearest, dim3((unsigned)((nq + per - 1) / per)), dim3(kBlock), 0, s, m, q, nq, hints,
-                       inv, idx, d2, radius);
+    const int per = kBlock / lanes;
+    const dim3 grid((unsigned)((nq + per - 1) / per));
+    switch (lanes) {
+    case 2: hipLaunchKernelGGL(k_map_nearest<2>, grid, dim3(kBlock), 0, s, m, q, nq, hints, inv, idx, d2, radius); break;
+    case 4: hipLaunchKernelGGL(k_map_nearest<4>, grid, dim3(kBlock), 0, s, m, q, nq, hints, inv, idx, d2, radius); break;
+    case 8: hipLaunchKernelGGL(k_map_nearest<8>, grid, dim3(kBlock), 0, s, m, q, nq, hints, inv, idx, d2, radius); break;
+    case 16: hipLaunchKernelGGL(k_map_nearest<16>, grid, dim3(kBlock), 0, s, m, q, nq, hints, inv, idx, d2, radius); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

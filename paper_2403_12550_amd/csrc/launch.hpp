@@ -223,8 +223,9 @@ hipError_t launch_overlap(const MapView& m, const float* src, int64_t n, const P
 // Correspondence search of the batched linearisation for arbitrary queries
 // (map frame, SoA [3][nq]); hints are map indices (inv: index -> sorted
 // position, required with hints); radius nullable.
+// lanes: 2 (the search of the batched launches) or 4, 8, 16 (the wide search).
 hipError_t launch_map_nearest(const MapView& m, const float* q, int64_t nq, const int32_t* hints, const int32_t* inv,
-                              int32_t* idx, float* d2, float* radius, hipStream_t s);
+                              int32_t* idx, float* d2, float* radius, int lanes, hipStream_t s);
 // inv[index of the point at sorted position j] = j for the m points of a map.
 hipError_t launch_map_inverse(const float4* spts, int64_t m, int32_t* inv, hipStream_t s);
 // Kept points -> map-frame means and scale-aligned, rotated covariances at

@@ -112,8 +112,9 @@ def test_c2_frame_to_map_nearest_sampled(g, ctx, c2):
     assert (d2.cpu().numpy()[s].view(np.uint32) == ek.view(np.uint32)).all()
 
 
+@pytest.mark.parametrize("lanes", [2, 4])
 @pytest.mark.parametrize("offset", [False, True])
-def test_c2_map_nearest_sampled(g, ctx, c2, offset):
+def test_c2_map_nearest_sampled(g, ctx, c2, offset, lanes):
     """The registration's own correspondence search (gicp_map_nearest) for a
     whole frame against the 1M-Gaussian map handle, at the true pose and at a
     pose 5 cm / 2 deg off; 5000 sampled rows bit-exact against the oracle's
@@ -126,9 +127,9 @@ def test_c2_map_nearest_sampled(g, ctx, c2, offset):
     if offset:
         T = T @ synth.random_offset(np.random.default_rng(7), 2.0, 0.05, exact=True)
     q = (p.astype(np.float64) @ T[:3, :3].T + T[:3, 3]).astype(np.float32)
-    _say("c2 map_nearest", q.shape[0], offset)
+    _say("c2 map_nearest", q.shape[0], offset, lanes)
     Q = g.to_soa(q)
-    idx, d2, rad = ctx.map_nearest(gm, Q, R_MAX, want_radius=True)
+    idx, d2, rad = ctx.map_nearest(gm, Q, R_MAX, want_radius=True, lanes=lanes)
     s = _sample(q.shape[0], 5000, 4)
     ei, ek = ok.knn_kdtree(seq.map_means, q[s], 1)
     gate = np.float32(np.float32(R_MAX) * np.float32(R_MAX))
@@ -142,7 +143,7 @@ def test_c2_map_nearest_sampled(g, ctx, c2, offset):
     for name, h in (("previous", np.where(full >= 0, full, -1)),
                     ("random", rng.integers(0, gm.m, q.shape[0])),
                     ("invalid", np.full(q.shape[0], gm.m + 1))):
-        hi, hd, _ = ctx.map_nearest(gm, Q, R_MAX, hints=torch.from_numpy(h.astype(np.int32)).cuda())
+        hi, hd, _ = ctx.map_nearest(gm, Q, R_MAX, hints=torch.from_numpy(h.astype(np.int32)).cuda(), lanes=lanes)
         assert (hi.cpu().numpy() == full).all(), name
         assert (hd.cpu().numpy().view(np.uint32) == d2.cpu().numpy().view(np.uint32)).all(), name
     r = rad.cpu().numpy()

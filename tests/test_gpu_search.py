@@ -59,16 +59,16 @@ def _hint_sets(rng, m, exact):
             "invalid": np.where(rng.random(nq) < 0.5, -1, m + 7).astype(np.int32)}
 
 
-def _check_nearest(g, ctx, gm, mpts, q, r_max, seed=0):
+def _check_nearest(g, ctx, gm, mpts, q, r_max, seed=0, lanes=0):
     import torch
     ei, ek = ok.knn_bruteforce(mpts, q, 1, r_max=r_max)
     Q = _soa(g, q)
-    idx, d2, rad = ctx.map_nearest(gm, Q, r_max, want_radius=True)
+    idx, d2, rad = ctx.map_nearest(gm, Q, r_max, want_radius=True, lanes=lanes)
     assert (idx.cpu().numpy() == ei[:, 0]).all()
     assert (d2.cpu().numpy().view(np.uint32) == ek[:, 0].view(np.uint32)).all()
     rng = np.random.default_rng(seed)
     for name, h in _hint_sets(rng, mpts.shape[0], np.where(ei[:, 0] >= 0, ei[:, 0], 0)).items():
-        hi, hd, _ = ctx.map_nearest(gm, Q, r_max, hints=torch.from_numpy(h).cuda())
+        hi, hd, _ = ctx.map_nearest(gm, Q, r_max, hints=torch.from_numpy(h).cuda(), lanes=lanes)
         assert (hi.cpu().numpy() == ei[:, 0]).all(), name
         assert (hd.cpu().numpy().view(np.uint32) == ek[:, 0].view(np.uint32)).all(), name
     return idx.cpu().numpy(), rad.cpu().numpy()
@@ -89,15 +89,18 @@ def _check_radius(mpts, q, idx, rad, seed, reps=4):
     return sel.size
 
 
+@pytest.mark.parametrize("lanes", [2, 4, 16])
 @pytest.mark.parametrize("cell", [0.03, 0.1, 0.4])
-def test_map_nearest_c1_bit_exact(g, ctx, cell):
-    """C1 target as the map; the source at the identity and at the true pose."""
+def test_map_nearest_c1_bit_exact(g, ctx, cell, lanes):
+    """C1 target as the map; the source at the identity and at the true pose
+    (two lanes per query as in two-lane launches; four and sixteen as in the
+    tracking launches)."""
     pr = synth.c1_problem()
     gm = _map(g, ctx, pr.tgt, cell)
     for k, T in enumerate((np.eye(4), pr.T_gt)):
         q = (pr.src.astype(np.float64) @ T[:3, :3].T + T[:3, 3]).astype(np.float32)
-        _say("map_nearest_c1", cell, k)
-        idx, rad = _check_nearest(g, ctx, gm, pr.tgt, q, 0.1, seed=k)
+        _say("map_nearest_c1", cell, lanes, k)
+        idx, rad = _check_nearest(g, ctx, gm, pr.tgt, q, 0.1, seed=k, lanes=lanes)
         assert 0.2 < (idx >= 0).mean() < 1.0
         _check_radius(pr.tgt, q, idx, rad, seed=10 + k)
     gm.close()
@@ -112,9 +115,10 @@ def test_map_nearest_lattice_ties(g, ctx, r_max):
     q = np.vstack([mp[rng.integers(0, mp.shape[0], 150)],
                    rng.integers(0, 12, (150, 3)).astype(np.float32) * np.float32(0.0625)]).astype(np.float32)
     for cell in (0.07, 0.125, 0.5):
-        _say("map_nearest_ties", r_max, cell)
         gm = _map(g, ctx, mp, cell, reg=0)
-        _check_nearest(g, ctx, gm, mp, q, r_max, seed=int(100 * r_max))
+        for lanes in (2, 4, 8, 16):
+            _say("map_nearest_ties", r_max, cell, lanes)
+            _check_nearest(g, ctx, gm, mp, q, r_max, seed=int(100 * r_max), lanes=lanes)
         gm.close()
 
 
@@ -124,8 +128,12 @@ def test_map_nearest_far_and_empty(g, ctx):
     pr = synth.c1_problem(n=3000)
     gm = _map(g, ctx, pr.tgt, 0.05)
     q = np.vstack([pr.src[:200], [[40, 0, 0], [0, -25, 3], [np.float32(1e3), 0, 0]]]).astype(np.float32)
-    _check_nearest(g, ctx, gm, pr.tgt, q, 0.1)
-    _check_nearest(g, ctx, gm, pr.tgt, q, 5.0)
+    for lanes in (2, 4, 16):
+        _say("map_nearest_far", lanes)
+        _check_nearest(g, ctx, gm, pr.tgt, q, 0.1, lanes=lanes)
+        _check_nearest(g, ctx, gm, pr.tgt, q, 5.0, lanes=lanes)
+    with pytest.raises(g.GicpError):
+        ctx.map_nearest(gm, _soa(g, q), 0.1, lanes=3)
     idx, d2, _ = ctx.map_nearest(gm, _soa(g, np.zeros((0, 3))), 0.1)
     assert idx.numel() == 0 and d2.numel() == 0
     gm.close()
@@ -145,6 +153,7 @@ def test_map_nearest_after_insert(g, ctx):
     assert (a.cpu().numpy() == ei[:, 0]).all()
     ctx.map_insert(gm, _soa(g, pr.tgt[3500:]), _soa(g, cov[3500:]))
     _check_nearest(g, ctx, gm, pr.tgt, q, 0.1)
+    _check_nearest(g, ctx, gm, pr.tgt, q, 0.1, lanes=4)
     gm.close()
 
 
@@ -160,11 +169,12 @@ def test_no_reuse_bitwise_c1(g, ctx, seed):
     src, tgt = _soa(g, pr.src), _soa(g, pr.tgt)
     tcov = ctx.covariances(tgt, 20, reg_mode=1, eps=1e-3)
     gm = ctx.map_build(tgt, tcov, cell=0.1)
-    for flags in (0, g.FLAG_MULTI_LAUNCH, g.FLAG_GRAPH, g.FLAG_QUEUE):
-        _say("no_reuse_c1", seed, flags)
-        a = ctx.register(src, gm, pr.init, g.params(max_it=30, flags=flags))
-        b = ctx.register(src, gm, pr.init, g.params(max_it=30, flags=flags | g.FLAG_NO_REUSE))
-        assert a.status == 0 and _same(a, b), flags
+    for lanes in (0, 4):
+        for flags in (0, g.FLAG_MULTI_LAUNCH, g.FLAG_GRAPH, g.FLAG_QUEUE):
+            _say("no_reuse_c1", seed, lanes, flags)
+            a = ctx.register(src, gm, pr.init, g.params(max_it=30, flags=flags, lanes=lanes))
+            b = ctx.register(src, gm, pr.init, g.params(max_it=30, flags=flags | g.FLAG_NO_REUSE, lanes=lanes))
+            assert a.status == 0 and _same(a, b), (lanes, flags)
     gm.close()
 
 
