@@ -298,6 +298,165 @@ __device__ __forceinline__ int32_t nearest(const MapView& m, float qx, float qy,
     return res;
 }
 
+// The same search by a group of four lanes that scan cells together: in each
+// round every lane takes one cell (the block's cells nearest first, then the
+// shells'), tests it against the group's bound and looks it up, and the
+// group then loads the round's candidates as one sequence, lane l taking
+// candidates l, l + 4, l + 8, ...: the four lanes of a point read adjacent
+// slots of the same cells, so that a wavefront's load touches about a
+// quarter of the cache lines that four separate cell scans touch, and the
+// group shares its best after every round, pruning the later cells with it.
+// The result is the same exact (key, index) minimum, and the certified
+// radius stays a valid bound (every mean is scanned, in a pruned cell, or
+// beyond the block clearance).
+template <bool TRACK2>
+__device__ __forceinline__ int32_t nearest_coop4(const MapView& m, float qx, float qy, float qz, int l, int32_t hint,
+                                                 float* free_r) {
+    constexpr int G = 4;
+    constexpr int kB = 6;
+    const GridView& g = m.g;
+    const bool fin = finite3(qx, qy, qz);
+    const int lane0 = (int)(threadIdx.x & 63u) & ~(G - 1);
+    uint64_t best = kEmptyWord, sec = kEmptyWord;
+    int32_t pos = -1;
+    float minlb = FLT_MAX;
+    if (fin && hint >= 0 && hint < g.n) {
+        const float4 p = gload(g.spts, hint);
+        best = word(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w));
+        pos = hint;
+    }
+    const Cell c = cell_of(fin ? qx : 0.f, fin ? qy : 0.f, fin ? qz : 0.f, g.inv_h);
+    const float slack = cell_slack(qx, qy, qz, kMaxShell, g.h);
+    // one round: this lane's cell (when `own`), then the group's candidates
+    auto round = [&](bool own, int cx, int cy, int cz) __attribute__((always_inline)) {
+        uint32_t st = 0, cnt = 0;
+        if (own) {
+            const float lb = cell_lower_bound2(qx, qy, qz, cx, cy, cz, g.h, slack);
+            if (cell_pruned(lb, fminf(key_of(best), m.r_max2))) {
+                if (TRACK2) minlb = fminf(minlb, lb);
+            } else {
+                cnt = cell_lookup(g.table, g.mask, cell_key(cx, cy, cz), st);
+            }
+        }
+        const uint32_t c0 = (uint32_t)__shfl((int)cnt, lane0, 64), c1 = (uint32_t)__shfl((int)cnt, lane0 + 1, 64);
+        const uint32_t c2 = (uint32_t)__shfl((int)cnt, lane0 + 2, 64), c3 = (uint32_t)__shfl((int)cnt, lane0 + 3, 64);
+        const uint32_t p1 = c0, p2 = p1 + c1, p3 = p2 + c2, total = p3 + c3;
+        if (total) {
+            // candidate t of the round sits at sorted position t + b(t), b the
+            // offset of the cell holding it
+            const uint32_t b0 = (uint32_t)__shfl((int)st, lane0, 64);
+            const uint32_t b1 = (uint32_t)__shfl((int)st, lane0 + 1, 64) - p1;
+            const uint32_t b2 = (uint32_t)__shfl((int)st, lane0 + 2, 64) - p2;
+            const uint32_t b3 = (uint32_t)__shfl((int)st, lane0 + 3, 64) - p3;
+            // (selects: the empty asm keeps the compiler from turning the
+            // chain into an indexed load from a stack copy of b0..b3)
+            auto at = [&](uint32_t t) __attribute__((always_inline)) {
+                uint32_t x1 = b1, x2 = b2, x3 = b3;
+                asm("" : "+v"(x1), "+v"(x2), "+v"(x3));
+                uint32_t b = t >= p1 ? x1 : b0;
+                b = t >= p2 ? x2 : b;
+                b = t >= p3 ? x3 : b;
+                return (int32_t)(t + b);
+            };
+            const int32_t first = at(0u);
+            for (uint32_t t0 = 0; t0 < total; t0 += G * kB) {
+                float4 pb[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const uint32_t t = t0 + (uint32_t)(l + G * u);
+                    pb[u] = gload(g.spts, (int64_t)(t < total ? at(t) : first));
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const uint32_t t = t0 + (uint32_t)(l + G * u);
+                    if (t < total) {
+                        const int32_t pj = at(t);
+                        uint64_t v = word(rank_key(qx, qy, qz, pb[u].x, pb[u].y, pb[u].z), __float_as_uint(pb[u].w));
+                        if (TRACK2) v = pj == pos ? kEmptyWord : v;   // the hint, already counted
+                        take<TRACK2>(v, pj, best, pos, sec);
+                    }
+                }
+            }
+        }
+        if (TRACK2) group_min2<G>(best, pos, sec, minlb);
+        else group_min<G>(best, pos);
+    };
+    if (fin) {
+        for (int j0 = 0; j0 < 27; j0 += G) {
+            const int j = j0 + l;
+            int dx = 0, dy = 0, dz = 0;
+            if (j < 27) block_offset(j, dx, dy, dz);
+            round(j < 27, c.x + dx, c.y + dy, c.z + dz);
+        }
+    }
+    if (!fin) {
+        if (free_r) *free_r = -1.f;
+        return -1;
+    }
+    const float r_gate = m.r_max * 1.000001f + 1e-6f;
+    const int max_shell = min(max(kMaxShell, (int)ceilf(r_gate * g.inv_h) + 1), kMaxGateShells);
+    float clr_end = FLT_MAX;
+    for (int R = 1;; ++R) {
+        const float clr = block_clearance(qx, qy, qz, c, R, g.h);
+        if (clr > 0.f) {
+            if (clr >= r_gate) {
+                clr_end = clr;
+                break;
+            }
+            if (best != kEmptyWord) {
+                const float bk = key_of(best);
+                if (bk < clr * clr * (1.f - 1e-6f)) {
+                    clr_end = clr;
+                    break;
+                }
+            }
+        }
+        if (R >= max_shell) {
+            best = kEmptyWord;
+            sec = kEmptyWord;
+            pos = -1;
+            minlb = FLT_MAX;
+            for (int32_t jj = l; jj < g.n; jj += G) {
+                const float4 p = gload(g.spts, jj);
+                take<TRACK2>(word(rank_key(qx, qy, qz, p.x, p.y, p.z), __float_as_uint(p.w)), jj, best, pos, sec);
+            }
+            if (TRACK2) group_min2<G>(best, pos, sec, minlb);
+            else group_min<G>(best, pos);
+            break;
+        }
+        // the shell's cells in rounds of four, lane l taking the l-th of each
+        // (the walk over the box is the same in the four lanes)
+        const int S = R + 1;
+        int k = 0, pdx = 0, pdy = 0, pdz = 0;
+        for (int dz = -S; dz <= S; ++dz)
+            for (int dy = -S; dy <= S; ++dy)
+                for (int dx = -S; dx <= S; ++dx)
+                    if (max(max(abs(dx), abs(dy)), abs(dz)) == S) {
+                        if ((k & (G - 1)) == l) {
+                            pdx = dx;
+                            pdy = dy;
+                            pdz = dz;
+                        }
+                        if ((k & (G - 1)) == G - 1) round(true, c.x + pdx, c.y + pdy, c.z + pdz);
+                        ++k;
+                    }
+        if (k & (G - 1)) round((k & (G - 1)) > l, c.x + pdx, c.y + pdy, c.z + pdz);
+    }
+    const float bk = key_of(best);
+    const int32_t res = (pos >= 0 && bk <= m.r_max2) ? pos : -1;
+    if (TRACK2 && free_r) {
+        float fr = -1.f;
+        if (res >= 0) {
+            const float k2 = fminf(fminf(key_of(sec), minlb), clr_end * clr_end);
+            const float d1 = sqrtf(bk), d2 = sqrtf(k2);
+            const float mag = fmaxf(fmaxf(fabsf(qx), fabsf(qy)), fabsf(qz));
+            fr = 0.5f * (d2 * (1.f - 1e-5f) - d1 * (1.f + 1e-5f)) - 4e-6f * (1.f + mag);
+        }
+        *free_r = fr;
+    }
+    return res;
+}
+
 // Hand-over of values between workgroups of one launch without cache
 // write-back.  An agent-scope fence writes back the whole L2 of the XCD
 // (measured: a launch of 1,057 workgroups that each fence before a counter
@@ -498,7 +657,9 @@ __device__ __forceinline__ void search_listed(const ProbDev& P, int64_t c, int n
     const int64_t i = c * kChunk + pt;
     const float qx = s_q[pt][0], qy = s_q[pt][1], qz = s_q[pt][2];
     float free_r;
-    const int32_t pos = nearest<true, GS>(P.map, qx, qy, qz, l, s_hint[pt], &free_r);
+    int32_t pos;
+    if constexpr (GS == 4 && !COH) pos = nearest_coop4<true>(P.map, qx, qy, qz, l, s_hint[pt], &free_r);
+    else pos = nearest<true, GS>(P.map, qx, qy, qz, l, s_hint[pt], &free_r);
     if (l == 0) {
         if (COH) {
             sput<true>(P.nn_prev + i, pos);
@@ -617,16 +778,42 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 // ---------------------------------------------------------------------------
 // FP64 solve and update.
 // ---------------------------------------------------------------------------
+// 1 / sqrt(s) for s > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - s y^2) / 2 (each roughly doubles the correct bits), in
+// place of a square root and a division on the solve's single thread; tiny
+// arguments, outside the estimate's normal range, take the plain division.
+__device__ __forceinline__ double rsqrt_pos(double s) {
+    if (!(s > 1e-280)) return 1.0 / sqrt(s);
+    double y = __builtin_amdgcn_rsq(s);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-(s * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// The coefficients of the closed-form SE(3) exponential, A = sin(th)/th,
+// B = (1 - cos th)/th^2, C = (th - sin th)/th^3, are even power series in
+// th: below th = 0.25 their terms up to th^12 reach double precision (the
+// first omitted term is below 3e-21 of the sum), with no sine, cosine or
+// division on the solve's single thread; above, the closed forms.
+constexpr double kExpSeriesMax2 = 0.0625;
+
 __device__ __forceinline__ void exp_se3(const double xi[6], double T[16]) {
     const double wx = xi[0], wy = xi[1], wz = xi[2];
     const double th2 = wx * wx + wy * wy + wz * wz;
-    const double th = sqrt(th2);
     double A, B, C;
-    if (th < 1e-4) {
-        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    if (th2 < kExpSeriesMax2) {
+        // Horner in th^2 with the coefficients (-1)^k / (2k+1)!, (-1)^k / (2k+2)!, (-1)^k / (2k+3)!
+        A = 1.0 + th2 * (-1.0 / 6.0 + th2 * (1.0 / 120.0 + th2 * (-1.0 / 5040.0 + th2 * (1.0 / 362880.0 +
+            th2 * (-1.0 / 39916800.0 + th2 * (1.0 / 6227020800.0))))));
+        B = 0.5 + th2 * (-1.0 / 24.0 + th2 * (1.0 / 720.0 + th2 * (-1.0 / 40320.0 + th2 * (1.0 / 3628800.0 +
+            th2 * (-1.0 / 479001600.0 + th2 * (1.0 / 87178291200.0))))));
+        C = 1.0 / 6.0 + th2 * (-1.0 / 120.0 + th2 * (1.0 / 5040.0 + th2 * (-1.0 / 362880.0 + th2 * (1.0 / 39916800.0 +
+            th2 * (-1.0 / 6227020800.0 + th2 * (1.0 / 1307674368000.0))))));
     } else {
+        const double th = sqrt(th2);
         const double sn = sin(th), cs = cos(th);
         A = sn / th;
         B = (1.0 - cs) / th2;
@@ -724,8 +911,7 @@ __device__ __forceinline__ void solve_update_inl(const double* v, const double* 
             o->done = 1;
             return;
         }
-        Lr[7 * j] = sqrt(s);
-        inv[j] = 1.0 / Lr[7 * j];
+        inv[j] = rsqrt_pos(s);   // the pivot L_jj itself is never needed, only its reciprocal
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double r = H[6 * i + j];
@@ -1409,7 +1595,9 @@ __global__ __launch_bounds__(kBlock) void k_map_nearest(MapView m, const float* 
         if (h >= 0 && h < m.g.n) hint = inv[h];
     }
     float fr = -1.f;
-    const int32_t pos = nearest<true, G>(m, qx, qy, qz, l, hint, &fr);
+    int32_t pos;
+    if constexpr (G == 4) pos = nearest_coop4<true>(m, qx, qy, qz, l, hint, &fr);
+    else pos = nearest<true, G>(m, qx, qy, qz, l, hint, &fr);
     if (l == 0) {
         if (pos >= 0) {
             const float4 p = gload(m.g.spts, pos);
