@@ -49,11 +49,11 @@ TRACK_NAMES = {**GROUP_NAMES, 0: "k_slot_iterate"}
 # iteration over the launches that did work.
 # Valid for the kernels as they were when the counters were taken (None: not
 # taken for the current kernels).
-TRAFFIC_BYTES_PER_UNIT = {0: 305.1}
+TRAFFIC_BYTES_PER_UNIT = {0: 297.2}
 # Wavefront VALU instructions per unit from rocprofv3 SQ_INSTS_VALU on the same
 # runs (profiles/hbm_traffic__k_slot_iterate__c2_track_pmc.md), and the chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64
 # instruction per SIMD every 4 cycles (16 lanes a cycle) at 2.4 GHz.
-VALU_INSTS_PER_UNIT = {0: 102.2}
+VALU_INSTS_PER_UNIT = {0: 93.9}
 VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
 MOTION_NAMES = {0: "previous", 1: "constant_velocity"}
 
