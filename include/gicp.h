@@ -92,8 +92,9 @@ typedef struct gicp_params {
     int32_t precision;      /* gicp_precision */
     int32_t flags;          /* GICP_FLAG_* */
     int32_t lanes;          /* lanes per source point in the linearisation: 2 or 4, or 0 for the
-                               form's default (batched launches 2, work queue 4, gicp_track 4);
-                               the results do not depend on it */
+                               form's default (batched launches: 4 for a single problem, 2 for
+                               several; work queue 4; gicp_track 4); the results do not depend
+                               on it */
 } gicp_params;
 
 /* gicp_params.flags.  Default (0): each Gauss-Newton iteration of all the

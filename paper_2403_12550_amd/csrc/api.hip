@@ -736,6 +736,12 @@ bool valid_params(const gicp_params* prm) {
 
 // Lanes per source point: the parameter, or the form's default.
 int lanes_of(const gicp_params* prm, int dflt) { return prm->lanes ? prm->lanes : dflt; }
+// Default lanes of the Gauss-Newton launches for nprob problems: one problem
+// leaves most of the chip idle and its launches are latency-bound (four
+// lanes: 1.78k against 1.44k frames/s for per-frame registration of the
+// 68k-point C2 frames); batches are bound by instruction issue (two lanes:
+// 8.0k against 7.9k frames/s for 50 frames a call).
+int batch_lanes(int64_t nprob) { return nprob == 1 ? kTrackLanes : kBatchLanes; }
 
 // Work-queue workers that fit on the device at once (asked once per shape).
 int queue_workers(gicp_ctx* c, int acc, int lanes) {
@@ -1057,7 +1063,8 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
             check(launch_chunk_map(c->d_probs, nprob, chunk_prob, s));
             if (grid > chunks) check(launch_fill_i32(chunk_prob + chunks, grid - chunks, -1, s));
             hipGraphExec_t ge =
-                iteration_graph(c, nprob, grid, prm->max_it, prm->precision, lanes_of(prm, kBatchLanes), chunk_prob, part);
+                iteration_graph(c, nprob, grid, prm->max_it, prm->precision, lanes_of(prm, batch_lanes(nprob)), chunk_prob,
+                                part);
             const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, -2, s);
             check(hipGraphLaunch(ge, s));
             prof_close(c, pl, s);
@@ -1071,11 +1078,11 @@ void register_many(gicp_ctx* c, int nprob, const gicp_problem* probs, const gicp
                 // single-problem case marks its iterations, batches count all
                 const int pl = prof_open(c, GICP_PROF_LINEARIZE, 0.0, it, s);
                 check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision,
-                                                lanes_of(prm, kBatchLanes), true, false, s));
+                                                lanes_of(prm, batch_lanes(nprob)), true, false, s));
                 prof_close(c, pl, s);
                 const int ps = prof_open(c, GICP_PROF_SOLVE, 1.0, it, s);
                 check(launch_gn_iteration_batch(c->d_probs, nprob, chunk_prob, chunks, part, prm->precision,
-                                                lanes_of(prm, kBatchLanes), false, true, s));
+                                                lanes_of(prm, batch_lanes(nprob)), false, true, s));
                 prof_close(c, ps, s);
             }
         }
@@ -1202,7 +1209,7 @@ int gicp_register_dev(gicp_ctx* c, const float* src, const float* src_covs, int6
                 check(launch_chunk_map(c->dev_probs, 1, chunk_prob, s));
                 for (int it = 0; it < prm->max_it; ++it)
                     check(launch_gn_iteration_batch(c->dev_probs, 1, chunk_prob, chunks, part, prm->precision,
-                                                    lanes_of(prm, kBatchLanes), true, true, s));
+                                                    lanes_of(prm, batch_lanes(1)), true, true, s));
             }
         }
         check(launch_state_out(c->dev_state, c->d_err, pose, H, b, stats, s));
